@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark: RS(10,4) encode at bandwidth scale on one MI355X.
+
+Workload: Cauchy RS(10,4) over GF(2^8)/0x11D, 10 data blocks of 64 MiB of
+seeded uniform random bytes (640 MiB in), 4 parity blocks (256 MiB out), each
+block split into 8 contiguous strips.  One step = one ec_encode launch over
+the whole stripe with inputs resident in HBM.  The headline value is the
+compressed + fused + scheduled program; the plain bitmatrix program, a
+4-erasure decode, and a plain device copy run on the same data for
+comparison.
+
+Prints one JSON line (see the keys below).  ``--gpus`` above 1 is refused:
+this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "encode/decode GB/s (input bytes) and % HBM roofline, compressed SLP vs plain bitmatrix"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--block-mib", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=0, help="register slot budget (0 = library default)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
+    ap.add_argument("--only", choices=["all", "compressed", "plain"], default="all")
+    return ap.parse_args()
+
+
+def time_launches(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per launch
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d refused); "
+              "multi-GPU sharding is described in DESIGN.md" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no ROCm GPU visible", file=sys.stderr)
+        sys.exit(1)
+    E.lib()  # fails loudly if the HIP library is missing
+    n, p = 10, 4
+    S = args.block_mib << 20
+    gen = E.ec_matrix_cauchy(n, p)
+    stream = torch.cuda.current_stream()
+    data = W.device_blocks(n, S, seed=2021)
+    parity = W.empty_blocks(p, S)
+    torch.cuda.synchronize()
+    in_bytes = n * S
+    moved = (n + p) * S  # algorithmic bytes per launch: read n blocks, write p blocks
+
+    def measure(prog, ins, outs, decode=False):
+        f = (lambda: E.ec_decode(prog, ins, outs, S, stream)) if decode else \
+            (lambda: E.ec_encode(prog, ins, outs, S, stream))
+        ms = time_launches(f, args.steps, args.warmup, stream)
+        return ms
+
+    t0 = time.time()
+    comp = E.ec_compile_slp(n, p, gen, level=E.LEVEL_CO_FU_SCHED, slot_budget=args.slots)
+    compile_ms = (time.time() - t0) * 1e3
+    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.slots)
+
+    res = {}
+    if args.only in ("all", "compressed"):
+        res["compressed"] = measure(comp, data, parity)
+    if args.only in ("all", "plain"):
+        res["plain"] = measure(plain, data, parity)
+    extra = {}
+    if args.only == "all":
+        # decode of the worst 4-erasure set of data blocks (4 data blocks lost)
+        er = [2, 4, 5, 6]
+        dprog = E.ec_compile_slp(n, p, gen, er, slot_budget=args.slots)
+        blocks = data + parity
+        E.ec_encode(comp, data, parity, S, stream)
+        surv = [blocks[i] for i in dprog.in_blocks]
+        rec = W.empty_blocks(len(er), S)
+        ms_dec = measure(dprog, surv, rec, decode=True)
+        torch.cuda.synchronize()
+        for j, e in enumerate(er):
+            if not torch.equal(rec[j], blocks[e]):
+                raise SystemExit("bench.py: decode self-check failed for block %d" % e)
+        dmoved = (n + len(er)) * S
+        extra["decode"] = {"erased": er, "ms": ms_dec, "GB_s": in_bytes / ms_dec / 1e6,
+                           "hbm_frac": dmoved / ms_dec / 1e6 / HBM_PEAK_GBS,
+                           "n_xor2": dprog.info["n_xor2"], "plain_xor2": dprog.info["plain_xor2"]}
+        del rec
+        # plain device copy of the same number of bytes (read + write = moved)
+        src = torch.empty(moved // 2, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        ms_copy = time_launches(lambda: E.ec_device_copy(dst, src, src.numel(), stream), args.steps,
+                                args.warmup, stream)
+        extra["copy_ceiling_GB_s"] = 2 * src.numel() / ms_copy / 1e6
+        del src, dst
+
+    head = "compressed" if "compressed" in res else "plain"
+    ms = res[head]
+    gbs = in_bytes / ms / 1e6
+    achieved = moved / ms / 1e6
+    info = (comp if head == "compressed" else plain).info
+    out = {
+        "metric": METRIC,
+        "value": gbs,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "RS(10,4) encode, Cauchy GF(2^8)/0x11D, 10 x %d MiB data -> 4 x %d MiB parity"
+                        % (args.block_mib, args.block_mib),
+            "program": "compressed+fused+scheduled" if head == "compressed" else "plain bitmatrix",
+            "block_bytes": S,
+            "slots": info["slots"],
+            "n_xor2": info["n_xor2"],
+            "plain_xor2": info["plain_xor2"],
+            "loads_per_tile": info["n_loads"],
+            "compile_ms": compile_ms,
+        },
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if "plain" in res and head == "compressed":
+        pms = res["plain"]
+        out["plain"] = {"ms": pms, "GB_s": in_bytes / pms / 1e6, "hbm_frac": moved / pms / 1e6 / HBM_PEAK_GBS,
+                        "n_xor2": plain.info["n_xor2"], "loads_per_tile": plain.info["n_loads"]}
+        out["compressed_vs_plain"] = pms / ms
+    out.update(extra)
+    if "copy_ceiling_GB_s" in out:
+        out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GB_s"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_block_mib)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(block_mib: int):
+    """The oracle, as is, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    from paper_2108_02692_amd import workloads as W
+    S = block_mib << 20
+    data = W.host_blocks(10, S, seed=2021)
+    G = oracle.cauchy(10, 4)
+    t = time.time()
+    oracle.encode(G, 10, 4, data)
+    dt = time.time() - t
+    return {"value": 10 * S / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "RS(10,4) encode of 10 x %d MiB seeded random blocks, single-threaded C oracle, %.1f s"
+                      % (block_mib, dt)}
+
+
+if __name__ == "__main__":
+    main()

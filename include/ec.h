@@ -1,0 +1,195 @@
+/*
+ * ec.h -- C ABI of libec: RS(n,p) erasure coding over GF(2^8) executed as
+ * compiled XOR straight-line programs (SLPs) on an MI355X (gfx950) GPU.
+ *
+ * Method: Uezato, "Accelerating XOR-based Erasure Coding using Program
+ * Optimization Techniques" (SC'21).  A coding matrix is expanded into a GF(2)
+ * bitmatrix (Sec. 1), turned into an XOR straight-line program (Sec. 2, 4.1),
+ * compressed by XorRePair (Sec. 4.3-4.4), fused into multi-input XORs
+ * (Sec. 5.2), scheduled by a DFS post-order (Sec. 6.6) and then allocated to
+ * a bounded set of GPU register slots and emitted as device bytecode that a
+ * HIP kernel runs over every tile of every strip.
+ *
+ * Conventions shared by every entry point:
+ *  - Status codes only; nothing throws across the ABI.
+ *  - Data buffers (device memory) are owned by the caller; programs and
+ *    batches are owned by the library and freed with their *_free call,
+ *    only after the work queued on them has completed.
+ *  - Block layout: each block is one contiguous buffer of S bytes; strip c of
+ *    a block is bytes [c*S/8, (c+1)*S/8).  S must be a positive multiple of
+ *    128 (so every strip is a whole number of 16-byte lanes) and every block
+ *    pointer must be 16-byte aligned (EC_ERR_ALIGN otherwise).
+ *  - Symbols: for a byte offset k of the strips and bit b, block i carries
+ *    the field element sum_c bit_b(strip_c[k]) x^c; the code is linear over
+ *    these symbols (Sec. 1, the byte <-> bit-vector isomorphism).
+ *  - Field: GF(2^8) with x^8+x^4+x^3+x^2+1 (0x11D) (Sec. 7.1).
+ *  - Launch calls are asynchronous on the given HIP stream (NULL = default
+ *    stream); argument errors are reported synchronously, launch failures as
+ *    EC_ERR_DEVICE, device faults at the caller's next synchronisation.
+ */
+#ifndef EC_H
+#define EC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ec_program ec_program; /* compiled program: host IR + device bytecode */
+typedef struct ec_batch ec_batch;     /* prepared multi-stripe launch */
+typedef struct ihipStream_t *ec_stream; /* a hipStream_t */
+
+typedef enum {
+  EC_OK = 0,
+  EC_ERR_ARG = 1,               /* bad argument (null pointer, n/p out of range, ...) */
+  EC_ERR_ALIGN = 2,             /* block size not a multiple of 128 or pointer not 16-B aligned */
+  EC_ERR_TOO_MANY_ERASURES = 3, /* more than p blocks erased */
+  EC_ERR_SINGULAR = 4,          /* survivor submatrix of the generator is not invertible */
+  EC_ERR_NOMEM = 5,             /* host or device allocation failed */
+  EC_ERR_DEVICE = 6,            /* HIP runtime error (no device, launch failure) */
+  EC_ERR_UNSUPPORTED = 7,       /* option or size outside what the executor supports */
+  EC_ERR_CAPACITY = 8           /* program does not fit the register slot budget */
+} ec_status;
+
+/* Optimisation level of a compiled program (the stages of Sec. 7.5). */
+enum {
+  EC_LEVEL_PLAIN = 0,        /* one multi-input XOR per bitmatrix row (plain bitmatrix SLP) */
+  EC_LEVEL_CO = 1,           /* XorRePair-compressed, binary XORs (Sec. 4.4) */
+  EC_LEVEL_CO_FU = 2,        /* compressed then fused (Sec. 5.2) */
+  EC_LEVEL_CO_FU_SCHED = 3   /* compressed, fused, DFS-scheduled (Sec. 6.6); default */
+};
+
+/* Compression algorithm for levels >= EC_LEVEL_CO. */
+enum { EC_COMPRESS_XORREPAIR = 0, EC_COMPRESS_REPAIR = 1 };
+
+typedef struct {
+  uint32_t level;       /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
+  uint32_t slot_budget; /* register slots per lane for the executor: 0 = default (32);
+                           supported: 16, 24, 32, 40, 48 */
+  uint32_t compress;    /* EC_COMPRESS_*; default XorRePair */
+  uint32_t hoist;       /* max distance (in program ops) a strip load is issued ahead
+                           of its first use; 0 = default */
+} ec_compile_opts;
+
+typedef struct {
+  uint32_t n, p;        /* codec */
+  uint32_t n_in;        /* input blocks (n) */
+  uint32_t n_out;       /* output blocks (p for encode, number of erasures for decode) */
+  uint32_t n_stmt;      /* statements of the optimised SLP */
+  uint32_t n_xor2;      /* #xor: sum over statements of (arity - 1) (Sec. 4.1) */
+  uint32_t n_mem;       /* #M: sum over statements of (arity + 1) (Sec. 5.1) */
+  uint32_t nvar;        /* variables of the optimised SLP (Sec. 4.1; pebbles after Sec. 6.6) */
+  uint32_t plain_xor2;  /* #xor of the plain bitmatrix program (ones - rows) */
+  uint32_t slots;       /* register slots used by the executor (incl. the zero slot) */
+  uint32_t peak_live;   /* peak number of slots holding live values */
+  uint32_t n_loads;     /* strip loads per tile (>= inputs used; extra are reloads) */
+  uint32_t n_stores;    /* strip stores per tile (= 8 * n_out) */
+  uint32_t n_words;     /* bytecode words */
+  const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
+  const int *out_blocks; /* n_out block indices written, in argument order */
+} ec_program_info;
+
+/* Systematic Cauchy generator G = [I_n ; P], P[i][j] = 1/(i + (p + j)) over
+ * GF(2^8) (the configured coding matrix; any square submatrix of a Cauchy
+ * matrix is nonsingular, as Sec. 1 requires of the decode step).
+ * gen: caller buffer of (n+p)*n bytes, row-major.  Needs n >= 1, p >= 0,
+ * n + p <= 64.  */
+ec_status ec_matrix_cauchy(int n, int p, uint8_t *gen);
+
+/* Generator with parity rows P[r][j] = alpha^(r*j) (alpha = x): the reading
+ * of Sec. 7.1 under which the printed XOR counts of the paper's RS(10,4)
+ * programs are reproduced.  Same layout and limits as ec_matrix_cauchy. */
+ec_status ec_matrix_vandermonde(int n, int p, uint8_t *gen);
+
+/* Compile an XOR program for an encode (n_erased == 0) or for the erasure
+ * pattern `erased` (decode).  gen is the (n+p) x n generator (copied).
+ * Decode reads the n lowest-indexed surviving blocks and reconstructs every
+ * erased block, data or parity (Sec. 1: the surviving rows form M and
+ * M^-1 recovers the data).  Needs 1 <= n, 0 <= p, n + p <= 32 (the
+ * executor's block table).  Host-only: needs no GPU.  Thread-safe.
+ * Errors: EC_ERR_ARG (also for a duplicate or out-of-range erased index),
+ * EC_ERR_TOO_MANY_ERASURES (n_erased > p), EC_ERR_SINGULAR, EC_ERR_CAPACITY,
+ * EC_ERR_UNSUPPORTED (level / slot budget not supported), EC_ERR_NOMEM. */
+ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, int n_erased,
+                         const ec_compile_opts *opts /* NULL = defaults */, ec_program **out);
+
+/* Counts and block mapping of a compiled program (Sec. 4.1, 5.1, 6.2
+ * measures).  The arrays in *out stay valid until ec_program_free. */
+ec_status ec_program_query(const ec_program *prog, ec_program_info *out);
+
+/* Encode: data = n device pointers (blocks 0..n-1), parity = p device
+ * pointers (blocks n..n+p-1), each block_bytes long.  prog must be an
+ * encode program.  Parity buffers must not alias data buffers. */
+ec_status ec_encode(const ec_program *prog, const uint8_t *const *data, uint8_t *const *parity,
+                    size_t block_bytes, ec_stream stream);
+
+/* Decode: survivors = n device pointers in the order info.in_blocks;
+ * recovered = n_erased device pointers in the order info.out_blocks. */
+ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uint8_t *const *recovered,
+                    size_t block_bytes, ec_stream stream);
+
+void ec_program_free(ec_program *prog);
+const char *ec_status_str(ec_status s);
+
+/* ---- inspection (used by tests to check the compiler against the oracle) */
+
+/* Stage of the compilation pipeline to export. */
+enum {
+  EC_STAGE_PLAIN = 0, /* one statement per bitmatrix row */
+  EC_STAGE_CO = 1,    /* after (Xor)RePair */
+  EC_STAGE_FU = 2,    /* after XOR fusion */
+  EC_STAGE_SCHED = 3, /* after DFS scheduling */
+  EC_STAGE_EXEC = 4   /* the program the executor runs: the level's last stage, with
+                         temporaries unfolded until its live values fit the slot budget */
+};
+
+/* Export one stage as a flat int32 array:
+ *   [n_stmt, n_out, { var, arity, op_0 .. op_{arity-1} } * n_stmt, out_0 .. out_{n_out-1}]
+ * Terms: t >= 0 is a variable; t == -1 is the zero array; t <= -2 is input
+ * strip c = -t - 2 (strip c of input argument c / 8).  Output j*8+r is strip
+ * r of output argument j.  *len receives the needed length; nothing is
+ * written beyond cap.  Stages CO/FU/SCHED exist for levels >= CO. */
+ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, size_t cap, size_t *len);
+
+/* Device-to-device copy with a plain 16-byte-per-lane kernel: the HBM
+ * bandwidth ceiling that executor throughput is compared with, and the
+ * kernel used to calibrate byte counters.  bytes: multiple of 16; both
+ * pointers 16-byte aligned (EC_ERR_ALIGN) and not overlapping (EC_ERR_ARG).
+ * Asynchronous on `stream`. */
+ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream stream);
+
+/* The device bytecode the executor runs per tile (host copy). */
+ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, size_t *n_words);
+
+/* ---- batched execution: many stripes, one persistent launch */
+
+typedef struct {
+  const ec_program *prog; /* encode or decode program */
+  const uint8_t *const *in;  /* prog's n_in device block pointers */
+  uint8_t *const *out;       /* prog's n_out device block pointers */
+  size_t block_bytes;        /* multiple of 128 */
+} ec_stripe;
+
+/* Prepare a launch over n_stripes stripes: uploads the stripe descriptors
+ * and program bytecode to the device (synchronously, on `stream`).  The
+ * stripes' buffers must stay valid for every later ec_batch_launch.
+ * tile_bytes: bytes per strip handled by one work item (multiple of 1024;
+ * 0 = default).  Programs in one batch must share one slot budget. */
+ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
+                         ec_batch **out);
+
+/* Run the batch: one persistent kernel whose waves take work items from a
+ * device queue.  Capturable into a HIP graph (no allocation, no memset). */
+ec_status ec_batch_launch(ec_batch *batch, ec_stream stream);
+
+/* Number of work items and total input/output bytes of a batch. */
+ec_status ec_batch_query(const ec_batch *batch, size_t *n_items, size_t *in_bytes, size_t *out_bytes);
+
+void ec_batch_free(ec_batch *batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EC_H */

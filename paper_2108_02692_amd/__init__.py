@@ -1,0 +1,282 @@
+"""paper_2108_02692_amd -- XOR-SLP erasure coding on MI355X (gfx950).
+
+Thin ctypes binding over ``libec.so`` (C ABI in ``include/ec.h``).  Every
+step of coding runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch is used for device memory and streams: pass
+``torch.Tensor`` buffers (uint8, on a ROCm device) or raw integer pointers.
+
+The names mirror the C entry points (``ec_compile_slp``, ``ec_encode``,
+``ec_decode``, ...); ``Program`` is a small owner of an ``ec_program*``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import _build
+
+__all__ = [
+    "EcError", "Program", "ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp",
+    "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_device_copy", "lib",
+    "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
+    "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC",
+]
+
+LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
+COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
+STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
+
+STATUS = {
+    0: "EC_OK", 1: "EC_ERR_ARG", 2: "EC_ERR_ALIGN", 3: "EC_ERR_TOO_MANY_ERASURES", 4: "EC_ERR_SINGULAR",
+    5: "EC_ERR_NOMEM", 6: "EC_ERR_DEVICE", 7: "EC_ERR_UNSUPPORTED", 8: "EC_ERR_CAPACITY",
+}
+
+
+class EcError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__("%s: %s (%s)" % (what, self.name, ec_status_str(status)))
+
+
+class CompileOpts(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_uint32), ("slot_budget", ctypes.c_uint32),
+                ("compress", ctypes.c_uint32), ("hoist", ctypes.c_uint32)]
+
+
+class ProgramInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
+        "peak_live", "n_loads", "n_stores", "n_words")] + [
+        ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
+
+
+class Stripe(ctypes.Structure):
+    _fields_ = [("prog", ctypes.c_void_p), ("in_", ctypes.POINTER(ctypes.c_void_p)),
+                ("out", ctypes.POINTER(ctypes.c_void_p)), ("block_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libec.so (built in-tree on first use if missing)."""
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = ctypes.CDLL(path)
+        vp, u8p, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int)
+        st = ctypes.c_int
+        L.ec_matrix_cauchy.argtypes = [ctypes.c_int, ctypes.c_int, u8p]
+        L.ec_matrix_vandermonde.argtypes = [ctypes.c_int, ctypes.c_int, u8p]
+        L.ec_compile_slp.argtypes = [ctypes.c_int, ctypes.c_int, u8p, ip, ctypes.c_int,
+                                     ctypes.POINTER(CompileOpts), ctypes.POINTER(vp)]
+        L.ec_program_query.argtypes = [vp, ctypes.POINTER(ProgramInfo)]
+        L.ec_encode.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_size_t, vp]
+        L.ec_decode.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_size_t, vp]
+        L.ec_program_free.argtypes = [vp]
+        L.ec_program_free.restype = None
+        L.ec_status_str.argtypes = [st]
+        L.ec_status_str.restype = ctypes.c_char_p
+        L.ec_program_export.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_program_bytecode.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.ec_batch_build.argtypes = [ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.ec_batch_launch.argtypes = [vp, vp]
+        L.ec_batch_query.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_batch_free.argtypes = [vp]
+        L.ec_batch_free.restype = None
+        for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
+                     "ec_encode", "ec_decode", "ec_program_export", "ec_program_bytecode", "ec_batch_build", "ec_device_copy",
+                     "ec_batch_launch", "ec_batch_query"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def ec_status_str(s: int) -> str:
+    return lib().ec_status_str(int(s)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise EcError(rc, what)
+
+
+def _u8buf(n: int):
+    return (ctypes.c_uint8 * n)()
+
+
+def ec_matrix_cauchy(n: int, p: int):
+    """(n+p) x n generator [I; P] with P[i][j] = 1/(i + (p + j)), as a list of rows."""
+    buf = _u8buf((n + p) * n)
+    _check(lib().ec_matrix_cauchy(n, p, buf), "ec_matrix_cauchy")
+    return [list(buf[r * n:(r + 1) * n]) for r in range(n + p)]
+
+
+def ec_matrix_vandermonde(n: int, p: int):
+    buf = _u8buf((n + p) * n)
+    _check(lib().ec_matrix_vandermonde(n, p, buf), "ec_matrix_vandermonde")
+    return [list(buf[r * n:(r + 1) * n]) for r in range(n + p)]
+
+
+def _flat_gen(gen, n, p):
+    flat = [int(x) for row in gen for x in row]
+    if len(flat) != (n + p) * n:
+        raise ValueError("generator must be (n+p) x n")
+    return (ctypes.c_uint8 * len(flat))(*flat)
+
+
+def _ptr(x) -> int:
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    raise TypeError("expected a device tensor or an integer pointer")
+
+
+def _ptr_array(xs):
+    arr = (ctypes.c_void_p * max(1, len(xs)))()
+    for i, x in enumerate(xs):
+        arr[i] = _ptr(x)
+    return arr
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream) or None
+        except Exception:  # pragma: no cover - torch without a device
+            return None
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+class Program:
+    """Owner of a compiled ``ec_program``."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        info = ProgramInfo()
+        _check(lib().ec_program_query(self._h, ctypes.byref(info)), "ec_program_query")
+        self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_ if not f.endswith("blocks")}
+        self.in_blocks = [info.in_blocks[i] for i in range(info.n_in)]
+        self.out_blocks = [info.out_blocks[i] for i in range(info.n_out)]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().ec_program_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self, stage: int):
+        """Program of one pipeline stage: (stmts, outputs) with terms as in
+        ec_program_export (>= 0 variable, -1 zero, <= -2 input strip -t-2)."""
+        n = ctypes.c_size_t()
+        _check(lib().ec_program_export(self._h, stage, None, 0, ctypes.byref(n)), "ec_program_export")
+        buf = (ctypes.c_int32 * n.value)()
+        _check(lib().ec_program_export(self._h, stage, buf, n.value, ctypes.byref(n)), "ec_program_export")
+        v = list(buf)
+        ns, no = v[0], v[1]
+        i = 2
+        stmts = []
+        for _ in range(ns):
+            var, ar = v[i], v[i + 1]
+            stmts.append((var, v[i + 2:i + 2 + ar]))
+            i += 2 + ar
+        return stmts, v[i:i + no]
+
+    def bytecode(self):
+        w = ctypes.POINTER(ctypes.c_uint32)()
+        n = ctypes.c_size_t()
+        _check(lib().ec_program_bytecode(self._h, ctypes.byref(w), ctypes.byref(n)), "ec_program_bytecode")
+        return [w[i] for i in range(n.value)]
+
+
+def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
+                   compress: int = COMPRESS_XORREPAIR, hoist: int = 0) -> Program:
+    er = list(erased)
+    er_arr = (ctypes.c_int * max(1, len(er)))(*er)
+    opts = CompileOpts(level, slot_budget, compress, hoist)
+    h = ctypes.c_void_p()
+    _check(lib().ec_compile_slp(n, p, _flat_gen(gen, n, p), er_arr, len(er), ctypes.byref(opts), ctypes.byref(h)),
+           "ec_compile_slp")
+    return Program(h.value)
+
+
+def ec_encode(prog: Program, data, parity, block_bytes: int, stream=None):
+    """Enqueue an encode on ``stream`` (default: torch's current stream)."""
+    _check(lib().ec_encode(prog.handle, _ptr_array(data), _ptr_array(parity), block_bytes,
+                           _stream_handle(stream)), "ec_encode")
+
+
+def ec_decode(prog: Program, survivors, recovered, block_bytes: int, stream=None):
+    """Enqueue a decode; ``survivors`` in ``prog.in_blocks`` order, ``recovered``
+    in ``prog.out_blocks`` order."""
+    _check(lib().ec_decode(prog.handle, _ptr_array(survivors), _ptr_array(recovered), block_bytes,
+                           _stream_handle(stream)), "ec_decode")
+
+
+def ec_device_copy(dst, src, nbytes: int, stream=None):
+    """Plain device copy kernel (bandwidth ceiling / counter calibration)."""
+    _check(lib().ec_device_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)), "ec_device_copy")
+
+
+class Batch:
+    """Owner of an ``ec_batch`` (many stripes, one persistent launch)."""
+
+    def __init__(self, handle: int, keepalive):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keepalive
+        n_items, nin, nout = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().ec_batch_query(self._h, ctypes.byref(n_items), ctypes.byref(nin), ctypes.byref(nout)),
+               "ec_batch_query")
+        self.n_items, self.in_bytes, self.out_bytes = n_items.value, nin.value, nout.value
+
+    def launch(self, stream=None):
+        _check(lib().ec_batch_launch(self._h, _stream_handle(stream)), "ec_batch_launch")
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().ec_batch_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
+    """``stripes``: iterable of (Program, inputs, outputs, block_bytes)."""
+    stripes = list(stripes)
+    arr = (Stripe * max(1, len(stripes)))()
+    keep = []
+    for i, (prog, ins, outs, bb) in enumerate(stripes):
+        ia, oa = _ptr_array(ins), _ptr_array(outs)
+        keep += [prog, ia, oa]
+        arr[i].prog = prog.handle.value
+        arr[i].in_ = ctypes.cast(ia, ctypes.POINTER(ctypes.c_void_p))
+        arr[i].out = ctypes.cast(oa, ctypes.POINTER(ctypes.c_void_p))
+        arr[i].block_bytes = bb
+    h = ctypes.c_void_p()
+    _check(lib().ec_batch_build(arr, len(stripes), tile_bytes, _stream_handle(stream), ctypes.byref(h)),
+           "ec_batch_build")
+    return Batch(h.value, keep)

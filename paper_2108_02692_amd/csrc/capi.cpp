@@ -1,0 +1,310 @@
+// capi.cpp -- the C ABI of libec (declared in include/ec.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/ec.h"
+#include "bytecode.hpp"
+#include "exec.hpp"
+#include "gf.hpp"
+#include "sched.hpp"
+#include "slp.hpp"
+
+using namespace ec;
+
+struct ec_program {
+  int n = 0, p = 0;
+  bool decode = false;
+  int level = EC_LEVEL_CO_FU_SCHED;
+  int slots = 32;
+  std::vector<int> in_blocks, out_blocks;
+  Slp plain, co, fu, sched;  // pipeline stages (co/fu/sched empty for PLAIN)
+  const Slp *final_stage = nullptr;
+  Slp exec;                  // the program the executor runs (fitted to the slot budget)
+  SchedResult code;
+  ec_program_info info{};
+  std::mutex mu;
+  std::map<int, uint32_t *> dev_words;  // device -> bytecode copy
+
+  ~ec_program() {
+    for (auto &kv : dev_words) {
+      int cur = 0;
+      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
+        (void)hipFree(kv.second);
+        (void)hipSetDevice(cur);
+      }
+    }
+  }
+
+  // Device copy of the bytecode for the current device (uploaded once).
+  const uint32_t *device_words(ec_status *st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { *st = EC_ERR_DEVICE; return nullptr; }
+    std::lock_guard<std::mutex> g(mu);
+    auto it = dev_words.find(dev);
+    if (it != dev_words.end()) return it->second;
+    uint32_t *d = nullptr;
+    const size_t bytes = code.words.size() * sizeof(uint32_t);
+    if (hipMalloc((void **)&d, bytes) != hipSuccess) { *st = EC_ERR_NOMEM; return nullptr; }
+    if (hipMemcpy(d, code.words.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      *st = EC_ERR_DEVICE;
+      return nullptr;
+    }
+    dev_words[dev] = d;
+    return d;
+  }
+};
+
+namespace {
+
+bool supported_slots(uint32_t k) { return k == 16 || k == 24 || k == 32 || k == 40 || k == 48; }
+
+ec_status make_generator(int n, int p, uint8_t *gen, bool cauchy) {
+  if (!gen || n < 1 || p < 0 || n + p > 64) return EC_ERR_ARG;
+  const Mat g = cauchy ? cauchy_generator(n, p) : vandermonde_rows_generator(n, p);
+  std::memcpy(gen, g.data(), g.size());
+  return EC_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *const *out, size_t block_bytes,
+                 ec_stream stream) {
+  if (!prog || !in || !out) return EC_ERR_ARG;
+  const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+  if (block_bytes == 0 || block_bytes % 128 != 0) return EC_ERR_ALIGN;
+  if (block_bytes / 8 > 0x1FFFFFFFull) return EC_ERR_UNSUPPORTED;  // strip offsets must fit 32 bits
+  for (int i = 0; i < n_in; ++i)
+    if (!in[i]) return EC_ERR_ARG;
+    else if (!aligned16(in[i])) return EC_ERR_ALIGN;
+  for (int j = 0; j < n_out; ++j)
+    if (!out[j]) return EC_ERR_ARG;
+    else if (!aligned16(out[j])) return EC_ERR_ALIGN;
+  // outputs must not overlap inputs or each other
+  for (int j = 0; j < n_out; ++j) {
+    const uintptr_t a = (uintptr_t)out[j];
+    for (int i = 0; i < n_in; ++i) {
+      const uintptr_t b = (uintptr_t)in[i];
+      if (a < b + block_bytes && b < a + block_bytes) return EC_ERR_ARG;
+    }
+    for (int k = j + 1; k < n_out; ++k) {
+      const uintptr_t b = (uintptr_t)out[k];
+      if (a < b + block_bytes && b < a + block_bytes) return EC_ERR_ARG;
+    }
+  }
+  ec_status st = EC_OK;
+  const uint32_t *words = const_cast<ec_program *>(prog)->device_words(&st);
+  if (!words) return st;
+  ExecArgs a{};
+  for (int i = 0; i < n_in; ++i) a.blk[i] = (uint64_t)(uintptr_t)in[i];
+  for (int j = 0; j < n_out; ++j) a.blk[n_in + j] = (uint64_t)(uintptr_t)out[j];
+  a.prog = words;
+  a.n_in = (uint32_t)n_in;
+  a.strip_len = block_bytes / 8;
+  a.n_tiles = (uint32_t)((a.strip_len + kTileBytes - 1) / kTileBytes);
+  const int grid = (int)std::min<uint64_t>((a.n_tiles + 3) / 4, 1u << 20);
+  if (exec_launch(prog->slots, a, grid, (hipStream_t)stream) != 0) return EC_ERR_DEVICE;
+  return EC_OK;
+}
+
+void export_stage(const Slp &s, std::vector<int32_t> &v) {
+  auto term = [](int t) -> int32_t {
+    if (t == kZero) return -1;
+    if (is_const(t)) return -(t - kConstBase) - 2;
+    return t;
+  };
+  v.push_back((int32_t)s.stmts.size());
+  v.push_back((int32_t)s.outputs.size());
+  for (const Stmt &st : s.stmts) {
+    v.push_back(st.var);
+    v.push_back((int32_t)st.ops.size());
+    for (int o : st.ops) v.push_back(term(o));
+  }
+  for (int o : s.outputs) v.push_back(term(o));
+}
+
+}  // namespace
+
+extern "C" {
+
+ec_status ec_matrix_cauchy(int n, int p, uint8_t *gen) { return make_generator(n, p, gen, true); }
+ec_status ec_matrix_vandermonde(int n, int p, uint8_t *gen) { return make_generator(n, p, gen, false); }
+
+ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, int n_erased,
+                         const ec_compile_opts *opts, ec_program **out) {
+  if (!out) return EC_ERR_ARG;
+  *out = nullptr;
+  if (!gen || n < 1 || p < 0 || n + p > kMaxBlocks || n_erased < 0) return EC_ERR_ARG;
+  if (n_erased > 0 && !erased) return EC_ERR_ARG;
+  if (n_erased > p) return EC_ERR_TOO_MANY_ERASURES;
+  for (int i = 0; i < n_erased; ++i) {
+    if (erased[i] < 0 || erased[i] >= n + p) return EC_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (erased[j] == erased[i]) return EC_ERR_ARG;
+  }
+  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 32, EC_COMPRESS_XORREPAIR, 0};
+  if (opts) {
+    o = *opts;
+    if (o.slot_budget == 0) o.slot_budget = 32;
+  }
+  if (o.level > EC_LEVEL_CO_FU_SCHED || !supported_slots(o.slot_budget) || o.compress > EC_COMPRESS_REPAIR)
+    return EC_ERR_UNSUPPORTED;
+
+  std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
+  if (!prog) return EC_ERR_NOMEM;
+  prog->n = n;
+  prog->p = p;
+  prog->decode = n_erased > 0;
+  prog->level = (int)o.level;
+  prog->slots = (int)o.slot_budget;
+  const Mat g(gen, gen + (size_t)(n + p) * n);
+  Mat rows;
+  if (!prog->decode) {
+    rows.assign(g.begin() + (size_t)n * n, g.end());
+    for (int i = 0; i < n; ++i) prog->in_blocks.push_back(i);
+    for (int j = 0; j < p; ++j) prog->out_blocks.push_back(n + j);
+  } else {
+    std::vector<int> er(erased, erased + n_erased);
+    if (decode_rows(n, p, g, er, rows, prog->in_blocks) != 0) return EC_ERR_SINGULAR;
+    prog->out_blocks = er;
+  }
+  const int n_rows = (int)prog->out_blocks.size();
+  const std::vector<Bits> brows = bitmatrix_rows(n_rows, n, rows);
+  const int n_const = 8 * n;
+  prog->plain = plain_slp(brows, n_const);
+  prog->final_stage = &prog->plain;
+  if (o.level >= EC_LEVEL_CO) {
+    prog->co = xor_repair(brows, n_const, o.compress == EC_COMPRESS_XORREPAIR);
+    prog->final_stage = &prog->co;
+  }
+  if (o.level >= EC_LEVEL_CO_FU) {
+    prog->fu = fuse(prog->co);
+    prog->final_stage = &prog->fu;
+  }
+  if (o.level >= EC_LEVEL_CO_FU_SCHED) {
+    prog->sched = dfs_schedule(prog->fu);
+    prog->final_stage = &prog->sched;
+  }
+  // Every stage must still compute the bitmatrix rows (Sec. 4.1 semantics).
+  const std::vector<Bits> val = evaluate(*prog->final_stage);
+  for (size_t r = 0; r < brows.size(); ++r)
+    if (!(val[r] == brows[r])) return EC_ERR_UNSUPPORTED;
+
+  SchedOpts so;
+  so.slots = (int)o.slot_budget;
+  if (o.hoist) so.hoist = (int)o.hoist;
+  // Run the paper's program if its live values fit the register slots;
+  // otherwise unfold temporaries until they do, leaving slots for inputs.
+  prog->exec = *prog->final_stage;
+  int rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
+  for (int budget = so.slots - std::max(6, so.slots / 4); rc == -1 && budget >= 0; budget -= 2) {
+    prog->exec = fit_live_budget(*prog->final_stage, budget);
+    rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
+  }
+  if (rc == -1) return EC_ERR_CAPACITY;
+  if (rc != 0) return EC_ERR_UNSUPPORTED;
+  {
+    const std::vector<Bits> ev = evaluate(prog->exec);
+    for (size_t r = 0; r < brows.size(); ++r)
+      if (!(ev[r] == brows[r])) return EC_ERR_UNSUPPORTED;
+  }
+
+  ec_program_info &info = prog->info;
+  info.n = (uint32_t)n;
+  info.p = (uint32_t)p;
+  info.n_in = (uint32_t)prog->in_blocks.size();
+  info.n_out = (uint32_t)n_rows;
+  const Slp &f = prog->exec;
+  info.n_stmt = (uint32_t)f.stmts.size();
+  info.n_xor2 = (uint32_t)count_xor(f);
+  info.n_mem = (uint32_t)count_mem(f);
+  info.nvar = (uint32_t)dfs_pebbles(f);
+  info.plain_xor2 = (uint32_t)count_xor(prog->plain);
+  info.slots = (uint32_t)prog->code.slots_used;
+  info.peak_live = (uint32_t)prog->code.peak_live;
+  info.n_loads = (uint32_t)prog->code.n_loads;
+  info.n_stores = (uint32_t)prog->code.n_stores;
+  info.n_words = (uint32_t)prog->code.words.size();
+  info.in_blocks = prog->in_blocks.data();
+  info.out_blocks = prog->out_blocks.data();
+  *out = prog.release();
+  return EC_OK;
+}
+
+ec_status ec_program_query(const ec_program *prog, ec_program_info *out) {
+  if (!prog || !out) return EC_ERR_ARG;
+  *out = prog->info;
+  return EC_OK;
+}
+
+ec_status ec_encode(const ec_program *prog, const uint8_t *const *data, uint8_t *const *parity,
+                    size_t block_bytes, ec_stream stream) {
+  if (!prog || prog->decode) return EC_ERR_ARG;
+  return launch(prog, data, parity, block_bytes, stream);
+}
+
+ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uint8_t *const *recovered,
+                    size_t block_bytes, ec_stream stream) {
+  if (!prog || !prog->decode) return EC_ERR_ARG;
+  return launch(prog, survivors, recovered, block_bytes, stream);
+}
+
+void ec_program_free(ec_program *prog) { delete prog; }
+
+const char *ec_status_str(ec_status s) {
+  switch (s) {
+    case EC_OK: return "ok";
+    case EC_ERR_ARG: return "invalid argument";
+    case EC_ERR_ALIGN: return "block size not a multiple of 128 or pointer not 16-byte aligned";
+    case EC_ERR_TOO_MANY_ERASURES: return "more erasures than parity blocks";
+    case EC_ERR_SINGULAR: return "survivor matrix is singular";
+    case EC_ERR_NOMEM: return "out of memory";
+    case EC_ERR_DEVICE: return "HIP device error";
+    case EC_ERR_UNSUPPORTED: return "unsupported option or size";
+    case EC_ERR_CAPACITY: return "program exceeds the register slot budget";
+  }
+  return "unknown status";
+}
+
+ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, size_t cap, size_t *len) {
+  if (!prog || !len) return EC_ERR_ARG;
+  const Slp *s = nullptr;
+  switch (stage) {
+    case EC_STAGE_PLAIN: s = &prog->plain; break;
+    case EC_STAGE_CO: s = prog->level >= EC_LEVEL_CO ? &prog->co : nullptr; break;
+    case EC_STAGE_FU: s = prog->level >= EC_LEVEL_CO_FU ? &prog->fu : nullptr; break;
+    case EC_STAGE_SCHED: s = prog->level >= EC_LEVEL_CO_FU_SCHED ? &prog->sched : nullptr; break;
+    case EC_STAGE_EXEC: s = &prog->exec; break;
+    default: break;
+  }
+  if (!s) return EC_ERR_ARG;
+  std::vector<int32_t> v;
+  export_stage(*s, v);
+  *len = v.size();
+  if (buf) std::memcpy(buf, v.data(), std::min(cap, v.size()) * sizeof(int32_t));
+  return EC_OK;
+}
+
+ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream stream) {
+  if (!dst || !src || bytes == 0) return EC_ERR_ARG;
+  if (bytes % 16 || !aligned16(dst) || !aligned16(src)) return EC_ERR_ALIGN;
+  const uintptr_t a = (uintptr_t)dst, b = (uintptr_t)src;
+  if (a < b + bytes && b < a + bytes) return EC_ERR_ARG;
+  return copy_launch(src, dst, bytes, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
+}
+
+ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, size_t *n_words) {
+  if (!prog || !words || !n_words) return EC_ERR_ARG;
+  *words = prog->code.words.data();
+  *n_words = prog->code.words.size();
+  return EC_OK;
+}
+
+}  // extern "C"

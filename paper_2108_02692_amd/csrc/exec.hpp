@@ -1,0 +1,27 @@
+// exec.hpp -- launch interface of the gfx950 executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ec {
+
+constexpr int kMaxBlocks = 32;  // input + output blocks of one stripe
+constexpr int kTileBytes = 1024;  // bytes of each strip per wave (64 lanes x 16 B)
+
+// Kernel arguments of a single-stripe launch (passed by value).
+struct ExecArgs {
+  uint64_t blk[kMaxBlocks];  // n_in input block pointers, then the output block pointers
+  const uint32_t *prog;      // device bytecode, padded with HALT words
+  uint32_t n_in;             // input blocks
+  uint32_t n_tiles;          // ceil(strip_len / kTileBytes)
+  uint64_t strip_len;        // bytes per strip (block_bytes / 8), multiple of 16
+};
+
+// Launch the executor instance for `slots` register slots; 0 on success.
+int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t stream);
+
+// Device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned).
+int copy_launch(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
+
+}  // namespace ec

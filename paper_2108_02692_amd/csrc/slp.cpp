@@ -1,0 +1,368 @@
+// slp.cpp -- bitmatrix expansion, plain SLP, (Xor)RePair, XOR fusion and DFS
+// scheduling (Secs. 1, 2, 4, 5 and 6 of the paper).
+//
+// Readings of points the paper leaves open (also recorded in the design doc):
+//  * term order: temporaries by creation, all before constants; constants by
+//    strip index 8*block + strip (Sec. 4.3);
+//  * a pair's frequency is the number of original definitions holding both
+//    terms; ties go to the lexicographically smallest pair;
+//  * Rebuild (Sec. 4.4) scans every temporary, takes the one leaving the
+//    smallest remainder (ties: earliest), and its result replaces the
+//    definition only when strictly shorter;
+//  * fusion (Sec. 5.2) never unfolds a returned variable, splices the
+//    unfolded operands at the variable's position, cancels repeated operands
+//    and always unfolds the earliest eligible statement first.
+#include "slp.hpp"
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <unordered_map>
+
+namespace ec {
+
+std::vector<Bits> bitmatrix_rows(int rows, int cols, const Mat &m) {
+  std::vector<Bits> out((size_t)rows * 8);
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) {
+      const uint8_t e = m[(size_t)i * cols + j];
+      for (int c = 0; c < 8; ++c) {
+        const uint8_t col = gf::mul(e, (uint8_t)(1u << c));
+        for (int r = 0; r < 8; ++r)
+          if ((col >> r) & 1u) out[(size_t)8 * i + r].flip(8 * j + c);
+      }
+    }
+  return out;
+}
+
+Slp plain_slp(const std::vector<Bits> &rows, int n_const) {
+  Slp p;
+  p.n_const = n_const;
+  for (size_t r = 0; r < rows.size(); ++r) {
+    std::vector<int> ops;
+    for (int c = 0; c < n_const; ++c)
+      if (rows[r].test(c)) ops.push_back(kConstBase + c);
+    if (ops.empty()) {
+      p.outputs.push_back(kZero);
+      continue;
+    }
+    p.stmts.push_back({(int)r, ops});
+    p.outputs.push_back((int)r);
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------- (Xor)RePair
+Slp xor_repair(const std::vector<Bits> &rows, int n_const, bool rebuild) {
+  const int R = (int)rows.size();
+  int total = 0;
+  for (const Bits &b : rows) total += b.count();
+  // Dense term ids: temporaries [0, tcap), constant c -> tcap + c.  Each
+  // pairing shrinks the total definition size, so at most `total` temps.
+  const int tcap = total + 1;
+  const int D = tcap + n_const;
+  std::vector<uint16_t> cnt((size_t)D * D, 0);
+
+  std::vector<std::vector<int>> defs(R);
+  std::vector<char> active(R, 1);
+  std::vector<int> alias(R, kZero);
+  for (int i = 0; i < R; ++i)
+    for (int c = 0; c < n_const; ++c)
+      if (rows[i].test(c)) defs[i].push_back(tcap + c);
+
+  std::vector<std::pair<int, int>> temps;
+  std::vector<Bits> tval;
+  auto val = [&](int d) -> Bits {
+    if (d < tcap) return tval[d];
+    Bits b;
+    b.flip(d - tcap);
+    return b;
+  };
+  auto settle = [&]() {
+    for (int i = 0; i < R; ++i)
+      if (active[i] && defs[i].size() <= 1) {
+        alias[i] = defs[i].empty() ? -1 : defs[i][0];
+        active[i] = 0;
+      }
+  };
+  auto do_rebuild = [&](int i) {
+    Bits rem = rows[i];
+    std::vector<int> chosen;
+    for (;;) {
+      int best = -1, best_sz = rem.count();
+      for (int k = 0; k < (int)tval.size(); ++k) {
+        const int sz = (rem ^ tval[k]).count();
+        if (sz < best_sz) { best = k; best_sz = sz; }
+      }
+      if (best < 0) break;
+      rem = rem ^ tval[best];
+      chosen.push_back(best);
+    }
+    std::vector<int> nd(chosen.begin(), chosen.end());
+    for (int c = 0; c < n_const; ++c)
+      if (rem.test(c)) nd.push_back(tcap + c);
+    std::sort(nd.begin(), nd.end());
+    return nd;
+  };
+
+  settle();
+  for (;;) {
+    bool any = false;
+    for (int i = 0; i < R; ++i) any |= (bool)active[i];
+    if (!any) break;
+    // Most frequent pair, ties to the smallest (x, y).
+    int best_f = 0;
+    size_t best_key = (size_t)-1;
+    for (int i = 0; i < R; ++i) {
+      if (!active[i]) continue;
+      const std::vector<int> &d = defs[i];
+      for (size_t a = 0; a < d.size(); ++a)
+        for (size_t b = a + 1; b < d.size(); ++b) {
+          const size_t k = (size_t)d[a] * D + d[b];
+          const int c = ++cnt[k];
+          if (c > best_f || (c == best_f && k < best_key)) { best_f = c; best_key = k; }
+        }
+    }
+    for (int i = 0; i < R; ++i) {
+      if (!active[i]) continue;
+      const std::vector<int> &d = defs[i];
+      for (size_t a = 0; a < d.size(); ++a)
+        for (size_t b = a + 1; b < d.size(); ++b) cnt[(size_t)d[a] * D + d[b]] = 0;
+    }
+    const int x = (int)(best_key / D), y = (int)(best_key % D);
+    const int t = (int)temps.size();
+    temps.push_back({x, y});
+    tval.push_back(val(x) ^ val(y));
+    for (int i = 0; i < R; ++i) {
+      if (!active[i]) continue;
+      std::vector<int> &d = defs[i];
+      auto ix = std::lower_bound(d.begin(), d.end(), x);
+      auto iy = std::lower_bound(d.begin(), d.end(), y);
+      if (ix == d.end() || *ix != x || iy == d.end() || *iy != y) continue;
+      d.erase(iy);
+      d.erase(std::lower_bound(d.begin(), d.end(), x));
+      d.insert(std::lower_bound(d.begin(), d.end(), t), t);
+    }
+    if (rebuild)
+      for (int i = 0; i < R; ++i) {
+        if (!active[i]) continue;
+        std::vector<int> nd = do_rebuild(i);
+        if (nd.size() < defs[i].size()) defs[i] = nd;
+      }
+    settle();
+  }
+
+  auto term = [&](int d) { return d < 0 ? kZero : (d < tcap ? d : kConstBase + (d - tcap)); };
+  Slp out;
+  out.n_const = n_const;
+  for (int k = 0; k < (int)temps.size(); ++k)
+    out.stmts.push_back({k, {term(temps[k].first), term(temps[k].second)}});
+  for (int i = 0; i < R; ++i) out.outputs.push_back(term(alias[i]));
+  return out;
+}
+
+// ---------------------------------------------------------------- fusion
+static std::vector<int> cancel_ops(const std::vector<int> &ops) {
+  std::map<int, int> cnt;
+  for (int o : ops) ++cnt[o];
+  std::vector<int> out;
+  for (int o : ops)
+    if ((cnt[o] & 1) && std::find(out.begin(), out.end(), o) == out.end()) out.push_back(o);
+  return out;
+}
+
+Slp fuse(const Slp &in) {
+  Slp p = in;
+  std::set<int> outset(in.outputs.begin(), in.outputs.end());
+  for (;;) {
+    std::unordered_map<int, int> uses;
+    for (const Stmt &s : p.stmts)
+      for (int o : s.ops)
+        if (!is_const(o) && o != kZero) ++uses[o];
+    bool removed = false;
+    std::vector<Stmt> kept;
+    for (const Stmt &s : p.stmts) {
+      if (uses[s.var] == 0 && !outset.count(s.var)) { removed = true; continue; }
+      kept.push_back(s);
+    }
+    if (removed) { p.stmts.swap(kept); continue; }
+    int target = -1;
+    for (size_t i = 0; i < p.stmts.size(); ++i)
+      if (!outset.count(p.stmts[i].var) && uses[p.stmts[i].var] == 1) { target = (int)i; break; }
+    if (target < 0) break;
+    const Stmt v = p.stmts[target];
+    for (Stmt &w : p.stmts) {
+      auto it = std::find(w.ops.begin(), w.ops.end(), v.var);
+      if (it == w.ops.end()) continue;
+      std::vector<int> spliced(w.ops.begin(), it);
+      spliced.insert(spliced.end(), v.ops.begin(), v.ops.end());
+      spliced.insert(spliced.end(), it + 1, w.ops.end());
+      w.ops = cancel_ops(spliced);
+      break;
+    }
+    p.stmts.erase(p.stmts.begin() + target);
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------- DFS
+Slp dfs_schedule(const Slp &in) {
+  std::map<int, const Stmt *> by_var;
+  for (const Stmt &s : in.stmts) by_var[s.var] = &s;
+  std::set<int> used;
+  for (const Stmt &s : in.stmts)
+    for (int o : s.ops)
+      if (by_var.count(o)) used.insert(o);
+  std::vector<int> roots;
+  for (const auto &kv : by_var)
+    if (!used.count(kv.first)) roots.push_back(kv.first);  // map order = var order
+  std::set<int> seen;
+  Slp out;
+  out.n_const = in.n_const;
+  out.outputs = in.outputs;
+  for (int r : roots) {
+    std::vector<std::pair<int, bool>> stack{{r, false}};
+    while (!stack.empty()) {
+      auto [node, done] = stack.back();
+      stack.pop_back();
+      if (done) { out.stmts.push_back(*by_var[node]); continue; }
+      if (seen.count(node)) continue;
+      seen.insert(node);
+      stack.push_back({node, true});
+      std::vector<int> kids;
+      for (int o : by_var[node]->ops)
+        if (by_var.count(o)) kids.push_back(o);
+      std::sort(kids.begin(), kids.end());
+      for (auto it = kids.rbegin(); it != kids.rend(); ++it)
+        if (!seen.count(*it)) stack.push_back({*it, false});
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------- budget fitting
+namespace {
+
+// Live temporaries after each statement; returns the peak and the set live
+// at the (first) peak.
+int live_peak(const Slp &p, std::vector<int> *at_peak) {
+  std::unordered_map<int, int> last;
+  for (size_t i = 0; i < p.stmts.size(); ++i)
+    for (int o : p.stmts[i].ops)
+      if (!is_const(o) && o != kZero) last[o] = (int)i;
+  std::set<int> live;
+  int peak = 0;
+  for (size_t i = 0; i < p.stmts.size(); ++i) {
+    for (int o : p.stmts[i].ops) {
+      auto it = last.find(o);
+      if (it != last.end() && it->second == (int)i) live.erase(o);
+    }
+    if (last.count(p.stmts[i].var)) live.insert(p.stmts[i].var);
+    if ((int)live.size() > peak) {
+      peak = (int)live.size();
+      if (at_peak) at_peak->assign(live.begin(), live.end());
+    }
+  }
+  return peak;
+}
+
+}  // namespace
+
+int peak_live_temps(const Slp &p) { return live_peak(p, nullptr); }
+
+Slp fit_live_budget(const Slp &in, int budget) {
+  Slp p = dfs_schedule(in);
+  const std::set<int> outset(in.outputs.begin(), in.outputs.end());
+  for (;;) {
+    std::vector<int> live;
+    if (live_peak(p, &live) <= budget) return p;
+    std::unordered_map<int, int> uses, arity;
+    for (const Stmt &s : p.stmts) {
+      arity[s.var] = (int)s.ops.size();
+      for (int o : s.ops)
+        if (!is_const(o) && o != kZero) ++uses[o];
+    }
+    int best = -1;
+    long best_cost = 0;
+    for (int t : live) {
+      if (outset.count(t)) continue;
+      const long cost = (long)(uses[t] - 1) * (arity[t] - 1);
+      if (best < 0 || cost < best_cost || (cost == best_cost && t < best)) { best = t; best_cost = cost; }
+    }
+    if (best < 0) return p;  // only outputs live: nothing left to unfold
+    std::vector<int> tops;
+    for (const Stmt &s : p.stmts)
+      if (s.var == best) tops = s.ops;
+    std::vector<Stmt> kept;
+    for (Stmt s : p.stmts) {
+      if (s.var == best) continue;
+      auto it = std::find(s.ops.begin(), s.ops.end(), best);
+      if (it != s.ops.end()) {
+        std::vector<int> spliced(s.ops.begin(), it);
+        spliced.insert(spliced.end(), tops.begin(), tops.end());
+        spliced.insert(spliced.end(), it + 1, s.ops.end());
+        s.ops = cancel_ops(spliced);
+      }
+      kept.push_back(s);
+    }
+    p.stmts.swap(kept);
+    p = dfs_schedule(p);
+  }
+}
+
+// ---------------------------------------------------------------- measures
+std::vector<Bits> evaluate(const Slp &p) {
+  std::unordered_map<int, Bits> env;
+  auto val = [&](int t) {
+    Bits b;
+    if (t == kZero) return b;
+    if (is_const(t)) { b.flip(t - kConstBase); return b; }
+    return env.at(t);
+  };
+  for (const Stmt &s : p.stmts) {
+    Bits x;
+    for (int o : s.ops) x = x ^ val(o);
+    env[s.var] = x;
+  }
+  std::vector<Bits> out;
+  for (int t : p.outputs) out.push_back(val(t));
+  return out;
+}
+
+int count_xor(const Slp &p) {
+  int n = 0;
+  for (const Stmt &s : p.stmts) n += (int)s.ops.size() - 1;
+  return n;
+}
+
+int count_mem(const Slp &p) {
+  int n = 0;
+  for (const Stmt &s : p.stmts) n += (int)s.ops.size() + 1;
+  return n;
+}
+
+int dfs_pebbles(const Slp &p) {
+  // Pebble assignment of the DFS heuristic (Sec. 6.6): a statement takes a
+  // movable pebble (its node no longer needed and not a goal) when there is
+  // one, else a fresh pebble.  The count does not depend on which movable
+  // pebble is taken.
+  std::unordered_map<int, int> last_use;
+  for (size_t i = 0; i < p.stmts.size(); ++i)
+    for (int o : p.stmts[i].ops)
+      if (!is_const(o) && o != kZero) last_use[o] = (int)i;
+  std::set<int> goals;
+  for (int o : p.outputs)
+    if (!is_const(o) && o != kZero) goals.insert(o);
+  int free_cnt = 0, npeb = 0;
+  for (size_t i = 0; i < p.stmts.size(); ++i) {
+    const Stmt &s = p.stmts[i];
+    for (int o : s.ops)
+      if (!is_const(o) && o != kZero && last_use[o] == (int)i && !goals.count(o)) ++free_cnt;
+    if (free_cnt > 0) --free_cnt;
+    else ++npeb;
+    if (!goals.count(s.var) && !last_use.count(s.var)) ++free_cnt;
+  }
+  return npeb;
+}
+
+}  // namespace ec

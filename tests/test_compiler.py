@@ -1,0 +1,194 @@
+"""Product compiler (host side of libec) against the oracle, on the CPU.
+
+* bitmatrix / plain program: equal to the oracle's bitmatrix of the same
+  generator (the one deliberate cross-check of Sec. 1 (ii) between the two);
+* XorRePair, fusion, DFS stages: statement-for-statement equal to the
+  oracle's implementation of Secs. 4-6 (same readings of the tie-breaks);
+* the executed program and its device bytecode: the bitmatrix rows under the
+  set semantics of Sec. 4.1, checked by the independent bytecode simulator;
+* error handling of ec_compile_slp.
+"""
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import slp as S
+import paper_2108_02692_amd as E
+from bytecode_sim import simulate
+
+BIG = S.Compressed.BIG
+
+
+def oracle_rows(gen, n, p, erased=()):
+    G = np.array(gen, dtype=np.uint8)
+    if erased:
+        D, _ = oracle.decode_matrix(G, n, p, list(erased))
+    else:
+        D = G[n:]
+    return S.rows_from_bitmatrix(oracle.bitmatrix(D))
+
+
+def to_oracle_terms(stmts, outs):
+    """Product export terms -> oracle key space (temps as is, const c -> BIG+c)."""
+    def t(x):
+        if x == -1:
+            return S.ZERO
+        if x <= -2:
+            return BIG + (-x - 2)
+        return x
+    return [(v, [t(o) for o in ops]) for v, ops in stmts], [t(o) for o in outs]
+
+
+def eval_export(stmts, outs):
+    env = {}
+
+    def val(x):
+        if x == -1:
+            return 0
+        if x <= -2:
+            return 1 << (-x - 2)
+        return env[x]
+    for v, ops in stmts:
+        acc = 0
+        for o in ops:
+            acc ^= val(o)
+        env[v] = acc
+    return [val(o) for o in outs]
+
+
+CODECS = [(10, 4), (6, 3), (12, 4), (14, 4)]
+
+
+@pytest.mark.parametrize("n,p", CODECS)
+def test_generator_matches_oracle(n, p):
+    assert np.array_equal(np.array(E.ec_matrix_cauchy(n, p), dtype=np.uint8), oracle.cauchy(n, p))
+    assert np.array_equal(np.array(E.ec_matrix_vandermonde(n, p), dtype=np.uint8), oracle.vandermonde_rows(n, p))
+
+
+def sample_patterns(n, p, k, seed):
+    rng = random.Random(seed)
+    pats = [()]
+    allp = [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
+    pats += rng.sample(allp, k)
+    return pats
+
+
+@pytest.mark.parametrize("n,p", CODECS)
+def test_plain_program_is_oracle_bitmatrix(n, p):
+    gen = E.ec_matrix_cauchy(n, p)
+    for er in sample_patterns(n, p, 6, n):
+        prog = E.ec_compile_slp(n, p, gen, er, level=E.LEVEL_PLAIN)
+        stmts, outs = prog.export(E.STAGE_PLAIN)
+        assert eval_export(stmts, outs) == oracle_rows(gen, n, p, er)
+        if er:
+            assert prog.in_blocks == oracle.survivors(n, p, er)
+            assert prog.out_blocks == list(er)
+
+
+def test_paper_matrix_plain_counts():
+    gen = E.ec_matrix_vandermonde(10, 4)
+    enc = E.ec_compile_slp(10, 4, gen, level=E.LEVEL_PLAIN)
+    assert enc.info["plain_xor2"] == 755
+    dec = E.ec_compile_slp(10, 4, gen, [2, 4, 5, 6], level=E.LEVEL_PLAIN)
+    assert dec.info["plain_xor2"] == 1368
+
+
+def oracle_pipeline(rows, n_const, rebuild=True):
+    comp = S.repair(rows, n_const, xor_rebuild=rebuild)
+    st, outs = comp.to_program()
+    fu = S.fuse(st, outs, comp.is_const)
+    dfs = S.dfs_order(fu, outs, comp.is_const)
+    return (st, outs), fu, dfs
+
+
+@pytest.mark.parametrize("n,p,er,rebuild", [
+    (10, 4, (), True), (10, 4, (2, 4, 5, 6), True), (10, 4, (0, 13), True), (6, 3, (), True),
+    (6, 3, (1, 7, 8), True), (10, 4, (), False)])
+def test_stages_equal_oracle(n, p, er, rebuild):
+    gen = E.ec_matrix_cauchy(n, p)
+    rows = oracle_rows(gen, n, p, er)
+    (co_st, co_out), fu, dfs = oracle_pipeline(rows, 8 * n, rebuild)
+    prog = E.ec_compile_slp(n, p, gen, er, compress=E.COMPRESS_XORREPAIR if rebuild else E.COMPRESS_REPAIR)
+    got_co = to_oracle_terms(*prog.export(E.STAGE_CO))
+    assert got_co == (co_st, co_out)
+    got_fu, outs = to_oracle_terms(*prog.export(E.STAGE_FU))
+    assert got_fu == fu and outs == co_out
+    got_dfs, _ = to_oracle_terms(*prog.export(E.STAGE_SCHED))
+    assert got_dfs == dfs
+
+
+def test_paper_matrix_stages_equal_oracle():
+    gen = E.ec_matrix_vandermonde(10, 4)
+    rows = oracle_rows(gen, 10, 4)
+    (co_st, co_out), fu, dfs = oracle_pipeline(rows, 80)
+    prog = E.ec_compile_slp(10, 4, gen)
+    assert to_oracle_terms(*prog.export(E.STAGE_CO)) == (co_st, co_out)
+    assert to_oracle_terms(*prog.export(E.STAGE_SCHED))[0] == dfs
+
+
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
+@pytest.mark.parametrize("K", [16, 24, 32, 40, 48])
+def test_bytecode_simulates_to_bitmatrix(level, K):
+    n, p = 10, 4
+    gen = E.ec_matrix_cauchy(n, p)
+    for er in sample_patterns(n, p, 2, K + level):
+        prog = E.ec_compile_slp(n, p, gen, er, level=level, slot_budget=K)
+        rows = oracle_rows(gen, n, p, er)
+        stmts, outs = prog.export(E.STAGE_EXEC)
+        assert eval_export(stmts, outs) == rows
+        got = simulate(prog.bytecode(), K, 8 * n, 8 * len(prog.out_blocks))
+        assert [got[o] for o in range(len(rows))] == rows
+        assert prog.info["n_stores"] == len(rows)
+
+
+@pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])
+def test_bytecode_other_codecs(n, p):
+    gen = E.ec_matrix_cauchy(n, p)
+    for er in sample_patterns(n, p, 3, 7 * n):
+        prog = E.ec_compile_slp(n, p, gen, er, slot_budget=32)
+        rows = oracle_rows(gen, n, p, er)
+        got = simulate(prog.bytecode(), 32, 8 * n, 8 * len(prog.out_blocks))
+        assert [got[o] for o in range(len(rows))] == rows
+
+
+def test_hoist_option_keeps_semantics():
+    gen = E.ec_matrix_cauchy(10, 4)
+    rows = oracle_rows(gen, 10, 4)
+    for h in (1, 4, 64, 1000):
+        prog = E.ec_compile_slp(10, 4, gen, hoist=h)
+        got = simulate(prog.bytecode(), 32, 80, 32)
+        assert [got[o] for o in range(32)] == rows
+
+
+def test_compressed_beats_plain_in_xors():
+    gen = E.ec_matrix_cauchy(10, 4)
+    plain = E.ec_compile_slp(10, 4, gen, level=E.LEVEL_PLAIN)
+    co = E.ec_compile_slp(10, 4, gen)
+    assert co.info["n_xor2"] < plain.info["n_xor2"] == 1256
+
+
+def test_compile_errors():
+    gen = E.ec_matrix_cauchy(10, 4)
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, gen, [0, 1, 2, 3, 4])
+    assert e.value.name == "EC_ERR_TOO_MANY_ERASURES"
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, gen, [0, 0])
+    assert e.value.name == "EC_ERR_ARG"
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, gen, [14])
+    assert e.value.name == "EC_ERR_ARG"
+    bad = [list(r) for r in gen]
+    bad[10] = list(bad[11])
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, bad, [0, 1, 2, 3])
+    assert e.value.name == "EC_ERR_SINGULAR"
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, gen, slot_budget=20)
+    assert e.value.name == "EC_ERR_UNSUPPORTED"
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
+    assert e.value.name == "EC_ERR_ARG"

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP executor (through the C ABI) against the CPU oracle.
+
+Every comparison is byte-exact (the path is integer XOR only).  Inputs come
+from the seeded generators in ``paper_2108_02692_amd.workloads``; expected
+values come from the oracle only: parity blocks from ``oracle.encode`` and,
+for decode, the original blocks themselves (the oracle's encode of the data).
+"""
+import functools
+import itertools
+import os
+import random
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2108_02692_amd as E
+from paper_2108_02692_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    E.lib()
+
+
+def run_encode(prog, data_np, block_bytes, stream=None):
+    d = W.to_device(data_np)
+    par = W.empty_blocks(len(prog.out_blocks), block_bytes, fill=0xA5)
+    E.ec_encode(prog, d, par, block_bytes, stream)
+    torch.cuda.synchronize()
+    return [p.cpu().numpy() for p in par]
+
+
+def run_decode(prog, blocks_np, block_bytes):
+    surv = W.to_device([blocks_np[i] for i in prog.in_blocks])
+    rec = W.empty_blocks(len(prog.out_blocks), block_bytes, fill=0xA5)
+    E.ec_decode(prog, surv, rec, block_bytes)
+    torch.cuda.synchronize()
+    return [r.cpu().numpy() for r in rec]
+
+
+def assert_blocks_equal(got, want, what):
+    for j, (g, w) in enumerate(zip(got, want)):
+        if not np.array_equal(g, w):
+            bad = np.nonzero(g != w)[0]
+            raise AssertionError("%s: block %d differs at %d bytes, first at %d" % (what, j, bad.size, bad[0]))
+
+
+@functools.lru_cache(maxsize=None)
+def rs10_4_1mib():
+    n, p, S = 10, 4, 1 << 20
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=0)
+    return gen, data, oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+
+
+def compile_many(n, p, gen, patterns, **kw):
+    """Compile one program per pattern on host threads (the C call releases
+    the GIL)."""
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda er: E.ec_compile_slp(n, p, gen, er, **kw), patterns))
+
+
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
+@pytest.mark.parametrize("K", [16, 24, 32, 40, 48])
+def test_encode_rs10_4_1mib(level, K):
+    """RS(10,4) encode, 10 x 1 MiB blocks of seeded random bytes."""
+    n, p, S = 10, 4, 1 << 20
+    gen, data, want = rs10_4_1mib()
+    prog = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K)
+    assert_blocks_equal(run_encode(prog, data, S), want, "encode level %d K %d" % (level, K))
+
+
+@pytest.mark.parametrize("S", [128, 256, 1152, 8192 + 128, 3 * 8192, 65536 + 640])
+def test_encode_ragged_sizes(S):
+    """Block sizes that leave a partial tile (1 KiB per strip per wave)."""
+    n, p = 10, 4
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=S)
+    want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+    for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+        prog = E.ec_compile_slp(n, p, gen, level=level)
+        assert_blocks_equal(run_encode(prog, data, S), want, "encode S=%d level %d" % (S, level))
+
+
+@pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])
+def test_encode_other_codecs(n, p):
+    S = 64 * 1024
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=n * 10 + p)
+    want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+    for K in (24, 48):
+        prog = E.ec_compile_slp(n, p, gen, slot_budget=K)
+        assert_blocks_equal(run_encode(prog, data, S), want, "RS(%d,%d) K %d" % (n, p, K))
+
+
+def all_patterns(n, p):
+    return [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
+
+
+def test_decode_rs10_4_every_pattern():
+    """All 1470 erasure sets of <= 4 blocks (1001 of exactly 4); 2 KiB blocks.
+    Recovered blocks must equal the originals (data from the generator,
+    parity from the oracle)."""
+    n, p, S = 10, 4, 2048
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=7)
+    blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+    dev = W.to_device(blocks)
+    pats = all_patterns(n, p)
+    assert len(pats) == 1470
+    for er, prog in zip(pats, compile_many(n, p, gen, pats)):
+        rec = W.empty_blocks(len(er), S, fill=0xA5)
+        E.ec_decode(prog, [dev[i] for i in prog.in_blocks], rec, S)
+        torch.cuda.synchronize()
+        assert_blocks_equal([r.cpu().numpy() for r in rec], [blocks[e] for e in er], "decode %s" % (er,))
+
+
+@pytest.mark.parametrize("er", [(2, 4, 5, 6), (4, 5, 6, 7), (0, 1, 2, 3), (10, 11, 12, 13), (0, 13), (9,)])
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
+def test_decode_rs10_4_1mib(er, level):
+    n, p, S = 10, 4, 1 << 20
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=1)
+    blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+    prog = E.ec_compile_slp(n, p, gen, er, level=level)
+    assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], "decode %s" % (er,))
+
+
+@pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])
+def test_decode_other_codecs_sampled(n, p):
+    S = 4096
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=3 * n + p)
+    blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+    rng = random.Random(n)
+    for er in rng.sample(all_patterns(n, p), 40):
+        prog = E.ec_compile_slp(n, p, gen, er)
+        assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], "RS(%d,%d) %s" % (n, p, er))
+
+
+def test_encode_64mib_sampled():
+    """The benchmark's configuration (10 x 64 MiB, default program): outputs
+    checked on sampled strip offsets, each sample coded by the oracle."""
+    n, p, S = 10, 4, 64 << 20
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.device_blocks(n, S, seed=11)
+    par = W.empty_blocks(p, S, fill=0xA5)
+    for level in (E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN):
+        prog = E.ec_compile_slp(n, p, gen, level=level)
+        E.ec_encode(prog, data, par, S)
+        torch.cuda.synchronize()
+        L = S // 8
+        offs = [0, 1024, L // 2 + 48, L - 1024, L - 16]
+        mini = [W.strip_sample(b, offs, 16).cpu().numpy() for b in data]
+        want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, mini)
+        got = [W.strip_sample(b, offs, 16).cpu().numpy() for b in par]
+        assert_blocks_equal(got, want, "64 MiB level %d" % level)
+
+
+def test_outputs_fully_written_and_inputs_untouched():
+    n, p, S = 10, 4, 4096 + 128
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=5)
+    d = W.to_device(data)
+    prog = E.ec_compile_slp(n, p, gen)
+    for fill in (0x00, 0xFF, 0xA5):
+        par = W.empty_blocks(p, S, fill=fill)
+        E.ec_encode(prog, d, par, S)
+        torch.cuda.synchronize()
+        want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+        assert_blocks_equal([x.cpu().numpy() for x in par], want, "fill %x" % fill)
+    assert_blocks_equal([x.cpu().numpy() for x in d], data, "inputs")
+
+
+def test_two_streams_concurrently():
+    n, p, S = 10, 4, 1 << 18
+    gen = E.ec_matrix_cauchy(n, p)
+    prog_a = E.ec_compile_slp(n, p, gen)
+    prog_b = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=48)
+    da, db = W.host_blocks(n, S, seed=21), W.host_blocks(n, S, seed=22)
+    ta, tb = W.to_device(da), W.to_device(db)
+    pa, pb = W.empty_blocks(p, S), W.empty_blocks(p, S)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    E.ec_encode(prog_a, ta, pa, S, sa)
+    E.ec_encode(prog_b, tb, pb, S, sb)
+    torch.cuda.synchronize()
+    G = np.array(gen, dtype=np.uint8)
+    assert_blocks_equal([x.cpu().numpy() for x in pa], oracle.encode(G, n, p, da), "stream a")
+    assert_blocks_equal([x.cpu().numpy() for x in pb], oracle.encode(G, n, p, db), "stream b")
+
+
+def test_launch_argument_errors():
+    n, p, S = 10, 4, 4096
+    gen = E.ec_matrix_cauchy(n, p)
+    prog = E.ec_compile_slp(n, p, gen)
+    dec = E.ec_compile_slp(n, p, gen, [1])
+    d = W.empty_blocks(n, S, fill=0)
+    par = W.empty_blocks(p, S)
+    big = torch.zeros(S + 64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.EcError) as e:
+        E.ec_encode(prog, d, par, S - 64)
+    assert e.value.name == "EC_ERR_ALIGN"
+    with pytest.raises(E.EcError) as e:
+        E.ec_encode(prog, d[:-1] + [big[8:]], par, S)
+    assert e.value.name == "EC_ERR_ALIGN"
+    with pytest.raises(E.EcError) as e:
+        E.ec_encode(prog, d, par[:-1] + [d[0]], S)
+    assert e.value.name == "EC_ERR_ARG"
+    with pytest.raises(E.EcError) as e:
+        E.ec_decode(prog, d, par, S)
+    assert e.value.name == "EC_ERR_ARG"
+    with pytest.raises(E.EcError) as e:
+        E.ec_encode(dec, d, par, S)
+    assert e.value.name == "EC_ERR_ARG"
