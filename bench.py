@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
     ap.add_argument("--only", choices=["all", "compressed", "plain"], default="all")
+    ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = --slots)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every (level, slot budget) pair on the workload and print one line each")
     return ap.parse_args()
 
 
@@ -89,7 +92,16 @@ def main():
     t0 = time.time()
     comp = E.ec_compile_slp(n, p, gen, level=E.LEVEL_CO_FU_SCHED, slot_budget=args.slots)
     compile_ms = (time.time() - t0) * 1e3
-    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.slots)
+    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots or args.slots)
+    if args.sweep:
+        for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+            for K in (16, 24, 32, 40, 48):
+                pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K)
+                ms = measure(pr, data, parity)
+                print(json.dumps({"sweep": True, "level": level, "slots": K, "ms": ms, "GB_s": in_bytes / ms / 1e6,
+                                  "hbm_frac": moved / ms / 1e6 / HBM_PEAK_GBS, "n_xor2": pr.info["n_xor2"],
+                                  "loads": pr.info["n_loads"], "blocks": pr.info["n_words"] // 16 - 1}), flush=True)
+        return
 
     res = {}
     if args.only in ("all", "compressed"):

@@ -66,8 +66,9 @@ enum { EC_COMPRESS_XORREPAIR = 0, EC_COMPRESS_REPAIR = 1 };
 
 typedef struct {
   uint32_t level;       /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
-  uint32_t slot_budget; /* register slots per lane for the executor: 0 = default (32);
-                           supported: 16, 24, 32, 40, 48 */
+  uint32_t slot_budget; /* register slots per lane for the executor; supported: 16, 24, 32,
+                           40, 48; 0 = default: for the plain level the smallest budget
+                           leaving 8 prefetch slots beside the output rows, else 48 */
   uint32_t compress;    /* EC_COMPRESS_*; default XorRePair */
   uint32_t hoist;       /* max distance (in program ops) a strip load is issued ahead
                            of its first use; 0 = default */

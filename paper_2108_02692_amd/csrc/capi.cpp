@@ -149,10 +149,16 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     for (int j = 0; j < i; ++j)
       if (erased[j] == erased[i]) return EC_ERR_ARG;
   }
-  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 32, EC_COMPRESS_XORREPAIR, 0};
-  if (opts) {
-    o = *opts;
-    if (o.slot_budget == 0) o.slot_budget = 32;
+  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0};
+  if (opts) o = *opts;
+  if (o.slot_budget == 0) {
+    // Default budget: the broadcast form needs the output rows plus a ring of
+    // at least 8 prefetch slots; pulled programs use the largest budget.
+    const int rows = 8 * (n_erased > 0 ? n_erased : p);
+    o.slot_budget = 48;
+    if (o.level == EC_LEVEL_PLAIN)
+      for (uint32_t k : {16u, 24u, 32u, 40u, 48u})
+        if ((int)k >= rows + 8) { o.slot_budget = k; break; }
   }
   if (o.level > EC_LEVEL_CO_FU_SCHED || !supported_slots(o.slot_budget) || o.compress > EC_COMPRESS_REPAIR)
     return EC_ERR_UNSUPPORTED;
@@ -200,13 +206,21 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   SchedOpts so;
   so.slots = (int)o.slot_budget;
   if (o.hoist) so.hoist = (int)o.hoist;
-  // Run the paper's program if its live values fit the register slots;
-  // otherwise unfold temporaries until they do, leaving slots for inputs.
+  // The plain program runs in broadcast form (rows accumulate in slots, each
+  // input strip is loaded once) whenever the rows leave room for a ring of
+  // prefetch slots.  Compressed programs run as pulled statements: the
+  // level's own program if its live values fit the register slots, else
+  // with temporaries unfolded until they do, leaving slots for inputs.
   prog->exec = *prog->final_stage;
-  int rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
-  for (int budget = so.slots - std::max(6, so.slots / 4); rc == -1 && budget >= 0; budget -= 2) {
-    prog->exec = fit_live_budget(*prog->final_stage, budget);
+  int rc;
+  if (o.level == EC_LEVEL_PLAIN && n_rows * 8 + 2 <= so.slots) {
+    rc = schedule_broadcast(brows, n_const, so, prog->code);
+  } else {
     rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
+    for (int budget = so.slots - std::max(6, so.slots / 4); rc == -1 && budget >= 0; budget -= 2) {
+      prog->exec = fit_live_budget(*prog->final_stage, budget);
+      rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
+    }
   }
   if (rc == -1) return EC_ERR_CAPACITY;
   if (rc != 0) return EC_ERR_UNSUPPORTED;

@@ -46,12 +46,56 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
     else asm volatile(CODE : EC_G6 : __VA_ARGS__);                       \
   } while (0)
 
+// Defines the pinned registers (no initial value except acc = 0), so the
+// compiler never sees two groups holding one value and never copies them.
+#define EC_G2_OUT "={v[0:3]}"(acc), "={v[4:35]}"(g0), "={v[36:67]}"(g1)
+#define EC_G3_OUT EC_G2_OUT, "={v[68:99]}"(g2)
+#define EC_G4_OUT EC_G3_OUT, "={v[100:131]}"(g3)
+#define EC_G5_OUT EC_G4_OUT, "={v[132:163]}"(g4)
+#define EC_G6_OUT EC_G5_OUT, "={v[164:195]}"(g5)
+#define EC_ZERO_ACC "v_mov_b32_e32 v0, 0\n\tv_mov_b32_e32 v1, 0\n\tv_mov_b32_e32 v2, 0\n\tv_mov_b32_e32 v3, 0"
+#define EC_SLOT_INIT(K)                                              \
+  do {                                                               \
+    if constexpr (K == 16) asm volatile(EC_ZERO_ACC : EC_G2_OUT);    \
+    else if constexpr (K == 24) asm volatile(EC_ZERO_ACC : EC_G3_OUT); \
+    else if constexpr (K == 32) asm volatile(EC_ZERO_ACC : EC_G4_OUT); \
+    else if constexpr (K == 40) asm volatile(EC_ZERO_ACC : EC_G5_OUT); \
+    else asm volatile(EC_ZERO_ACC : EC_G6_OUT);                      \
+  } while (0)
+
+// Groups as inputs only (the statement reads slots but writes only acc).
+#define EC_GI2 "{v[4:35]}"(g0), "{v[36:67]}"(g1)
+#define EC_GI3 EC_GI2, "{v[68:99]}"(g2)
+#define EC_GI4 EC_GI3, "{v[100:131]}"(g3)
+#define EC_GI5 EC_GI4, "{v[132:163]}"(g4)
+#define EC_GI6 EC_GI5, "{v[164:195]}"(g5)
+#define EC_ACC_ASM(K, CODE, ...)                                                    \
+  do {                                                                              \
+    if constexpr (K == 16) asm volatile(CODE : "+{v[0:3]}"(acc) : EC_GI2, __VA_ARGS__); \
+    else if constexpr (K == 24) asm volatile(CODE : "+{v[0:3]}"(acc) : EC_GI3, __VA_ARGS__); \
+    else if constexpr (K == 32) asm volatile(CODE : "+{v[0:3]}"(acc) : EC_GI4, __VA_ARGS__); \
+    else if constexpr (K == 40) asm volatile(CODE : "+{v[0:3]}"(acc) : EC_GI5, __VA_ARGS__); \
+    else asm volatile(CODE : "+{v[0:3]}"(acc) : EC_GI6, __VA_ARGS__);             \
+  } while (0)
+
 #define SLOT_PARAMS v4u &acc, v32u &g0, v32u &g1, v32u &g2, v32u &g3, v32u &g4, v32u &g5
 #define SLOT_ARGS acc, g0, g1, g2, g3, g4, g5
 
 struct Win {
-  uint32_t w[bc::kWindow];
+  uint32_t w[bc::kBlockWords];
 };
+
+// The bytecode is read-only while a kernel runs: reading it through the
+// constant address space lets every block come through the scalar cache
+// (s_load_dwordx16), whatever the surrounding asm statements may touch.
+typedef const __attribute__((address_space(4))) Win *ConstWinPtr;
+__device__ __forceinline__ Win load_block(const uint32_t *prog, uint32_t pc) {
+  ConstWinPtr p = (ConstWinPtr)(uintptr_t)(prog + pc);
+  Win r;
+#pragma unroll
+  for (int i = 0; i < bc::kBlockWords; ++i) r.w[i] = p->w[i];
+  return r;
+}
 
 template <int K>
 __device__ __forceinline__ void issue_load(uint32_t slot, uint32_t voff, uint64_t base, SLOT_PARAMS);
@@ -296,9 +340,10 @@ __device__ __forceinline__ void issue_load<48>(uint32_t slot, uint32_t voff, uin
       [slot] "s"(slot), [off] "v"(voff), [base] "s"(base) : "s80", "s81", "s82", "scc");
 }
 
-template <int K>
-__device__ __forceinline__ void wait_vm(uint32_t n, SLOT_PARAMS) {
-  EC_SLOT_ASM(K,
+// s_waitcnt vmcnt(n) for a data-dependent n, through a jump table.  Touches
+// no register the compiler tracks.
+__device__ __forceinline__ void wait_vm(uint32_t n) {
+  asm volatile(
       "s_getpc_b64 s[80:81]\n"
       "1:\n\t"
       "s_lshl_b32 s82, %[n], 3\n\t"
@@ -371,71 +416,130 @@ __device__ __forceinline__ void wait_vm(uint32_t n, SLOT_PARAMS) {
       "s_waitcnt vmcnt(61)\n\ts_branch 3f\n\t"
       "s_waitcnt vmcnt(62)\n\ts_branch 3f\n\t"
       "s_waitcnt vmcnt(63)\n\ts_branch 3f\n\t"
-      "3:",
-      [n] "s"(n) : "s80", "s81", "s82", "scc");
+      "3:"
+      :: [n] "s"(n) : "s80", "s81", "s82", "scc");
 }
 
-// XOR the block's n operands (words 2 .. 2+n-1 of the window) into acc.
+// A run of n operand steps, entered by a computed jump that skips 14 - n of
+// the 14 unrolled 20-byte steps (each: s_set_gpr_idx_on + 4 VALU ops).
+#define EC_JUMP(L1, L2, SKIP)                          \
+  "s_getpc_b64 s[80:81]\n" L1 ":\n\t"                  \
+  "s_mul_i32 s82, " SKIP ", 20\n\t"                    \
+  "s_add_u32 s82, s82, " L2 "f-" L1 "b\n\t"            \
+  "s_add_u32 s80, s80, s82\n\t"                        \
+  "s_addc_u32 s81, s81, 0\n\t"                         \
+  "s_setpc_b64 s[80:81]\n" L2 ":\n\t"
+#define EC_WORDS                                                                                   \
+  [w2] "s"(W.w[2]), [w3] "s"(W.w[3]), [w4] "s"(W.w[4]), [w5] "s"(W.w[5]), [w6] "s"(W.w[6]),         \
+  [w7] "s"(W.w[7]), [w8] "s"(W.w[8]), [w9] "s"(W.w[9]), [w10] "s"(W.w[10]), [w11] "s"(W.w[11]),     \
+  [w12] "s"(W.w[12]), [w13] "s"(W.w[13]), [w14] "s"(W.w[14]), [w15] "s"(W.w[15])
+
+// acc ^= slot[w] for the n pull words (words 2 .. 2+n-1); n = 0 jumps past
+// every step.
 template <int K>
-__device__ __forceinline__ void xor_run(const Win &W, uint32_t n, SLOT_PARAMS) {
-  const uint32_t skip = (uint32_t)bc::kMaxOperands - n;
-  EC_SLOT_ASM(K,
-                "s_getpc_b64 s[80:81]\n"
-                "1:\n\t"
-                "s_mul_i32 s82, %[skip], 20\n\t"
-                "s_add_u32 s82, s82, 2f-1b\n\t"
-                "s_add_u32 s80, s80, s82\n\t"
-                "s_addc_u32 s81, s81, 0\n\t"
-                "s_setpc_b64 s[80:81]\n"
-                "2:\n\t"
-                "s_set_gpr_idx_on %[w15], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+__device__ __forceinline__ void pull_run(const Win &W, uint32_t n, SLOT_PARAMS) {
+  const uint32_t skip = __builtin_amdgcn_readfirstlane((uint32_t)bc::kMaxOperands - n);
+  EC_ACC_ASM(K, EC_JUMP("1", "2", "%[skip]") "s_set_gpr_idx_on %[w15], gpr_idx(SRC0)\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w14], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w13], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w12], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w11], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w10], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w9], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w8], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w7], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w6], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w5], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w4], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w3], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
                 "s_set_gpr_idx_on %[w2], gpr_idx(SRC0)\n\t"
-                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\t"
-                "v_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t"
-                "s_set_gpr_idx_off",
-                [skip] "s"(skip), [w2] "s"(W.w[2]), [w3] "s"(W.w[3]), [w4] "s"(W.w[4]), [w5] "s"(W.w[5]),
-                [w6] "s"(W.w[6]), [w7] "s"(W.w[7]), [w8] "s"(W.w[8]), [w9] "s"(W.w[9]),
-                [w10] "s"(W.w[10]), [w11] "s"(W.w[11]), [w12] "s"(W.w[12]), [w13] "s"(W.w[13]),
-                [w14] "s"(W.w[14]), [w15] "s"(W.w[15])
-                : "s80", "s81", "s82", "scc");
+                "v_xor_b32_e32 v0, v4, v0\n\tv_xor_b32_e32 v1, v5, v1\n\tv_xor_b32_e32 v2, v6, v2\n\tv_xor_b32_e32 v3, v7, v3\n\t" "s_set_gpr_idx_off",
+             [skip] "s"(skip), EC_WORDS : "s80", "s81", "s82", "scc");
+}
+
+// For the n push words (words 16-n .. 15): slot[w] ^= acc, or slot[w] = acc
+// when `set` is nonzero.  One asm statement for both forms, so the register
+// allocator sees a single producer of the slot registers.
+template <int K>
+__device__ __forceinline__ void push_run(const Win &W, uint32_t n, uint32_t set, SLOT_PARAMS) {
+  const uint32_t skip = __builtin_amdgcn_readfirstlane((uint32_t)bc::kMaxOperands - n);
+  const uint32_t is_set = __builtin_amdgcn_readfirstlane(set);
+  EC_SLOT_ASM(K,
+              "s_cmp_lg_u32 %[set], 0\n\t"
+              "s_cbranch_scc1 5f\n\t"
+              EC_JUMP("1", "2", "%[skip]") "s_set_gpr_idx_on %[w2], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w3], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w4], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w5], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w6], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w7], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w8], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w9], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w10], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w11], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w12], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w13], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w14], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t"
+                "s_set_gpr_idx_on %[w15], gpr_idx(SRC0,DST)\n\t"
+                "v_xor_b32_e32 v4, v4, v0\n\tv_xor_b32_e32 v5, v5, v1\n\tv_xor_b32_e32 v6, v6, v2\n\tv_xor_b32_e32 v7, v7, v3\n\t" "s_set_gpr_idx_off\n\t"
+              "s_branch 6f\n"
+              "5:\n\t"
+              EC_JUMP("3", "4", "%[skip]") "s_set_gpr_idx_on %[w2], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w3], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w4], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w5], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w6], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w7], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w8], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w9], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w10], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w11], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w12], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w13], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w14], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
+                "s_set_gpr_idx_on %[w15], gpr_idx(DST)\n\t"
+                "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\tv_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t" "s_set_gpr_idx_off\n"
+              "6:",
+              [skip] "s"(skip), [set] "s"(is_set), EC_WORDS : "s80", "s81", "s82", "scc");
 }
 
 __device__ __forceinline__ uint64_t strip_base(uint32_t tab_lo, uint32_t tab_hi, uint32_t blk, uint32_t strip,
@@ -445,43 +549,44 @@ __device__ __forceinline__ uint64_t strip_base(uint32_t tab_lo, uint32_t tab_hi,
   return p + (uint64_t)(strip * strip_len) + toff;
 }
 
-// Runs block `W` (at word `pc`) and prefetches the following block into
-// `next`; returns true at HALT.
+// Runs block `W` and prefetches the next one (blocks have a fixed size, so
+// its address is known at once); returns true at HALT.
 template <int K>
 __device__ __forceinline__ bool run_block(const uint32_t *__restrict__ prog, const Win &W, uint32_t &pc, Win &next,
                                           uint32_t voff, uint32_t tab_lo, uint32_t tab_hi, uint32_t n_in,
                                           uint32_t strip_len, uint64_t toff, SLOT_PARAMS) {
   const uint32_t h0 = W.w[0], h1 = W.w[1];
-  // Clamps keep every computed jump inside its table even for a corrupt
-  // program (the host validates every field; these cost one SALU each).
-  const uint32_t n = __builtin_amdgcn_readfirstlane(min(h0 & bc::H0_N, (uint32_t)bc::kMaxOperands));
-  pc += 2 + n;
-  next = *reinterpret_cast<const Win *>(prog + pc);
+  pc += bc::kBlockWords;
+  next = load_block(prog, pc);
   if (h0 & bc::H0_LD) {
     const uint32_t c = bc::h0_ld_strip(h0);
-    issue_load<K>(min(bc::h0_ld_slot(h0), (uint32_t)(K - 1)), voff, strip_base(tab_lo, tab_hi, c >> 3, c & 7u, strip_len, toff),
-                  SLOT_ARGS);
+    // slot clamped so the jump stays inside the table (the host validates it)
+    issue_load<K>(__builtin_amdgcn_readfirstlane(min(bc::h0_ld_slot(h0), (uint32_t)(K - 1))), voff,
+                  strip_base(tab_lo, tab_hi, c >> 3, c & 7u, strip_len, toff), SLOT_ARGS);
   }
-  if (h0 & bc::H0_WAIT) wait_vm<K>(bc::h0_wait(h0), SLOT_ARGS);  // 6-bit field: always in the table
-  xor_run<K>(W, n, SLOT_ARGS);
+  if (h0 & bc::H0_WAIT) wait_vm(__builtin_amdgcn_readfirstlane(bc::h1_wait(h1)));  // 6-bit field: always in the table
+  // run lengths clamped to the 14 unrolled steps
+  const uint32_t np = min(bc::h0_np(h0), (uint32_t)bc::kMaxOperands);
+  const uint32_t nq = min(bc::h0_nq(h0), (uint32_t)bc::kMaxOperands);
+  pull_run<K>(W, np, SLOT_ARGS);
   if (h1 & bc::H1_PUT) {
     EC_SLOT_ASM(K,
                 "s_set_gpr_idx_on %[i], gpr_idx(DST)\n\t"
                 "v_mov_b32_e32 v4, v0\n\tv_mov_b32_e32 v5, v1\n\t"
                 "v_mov_b32_e32 v6, v2\n\tv_mov_b32_e32 v7, v3\n\t"
                 "s_set_gpr_idx_off",
-                [i] "s"(min(bc::h1_put_slot(h1), (uint32_t)(K - 1)) * 4u));
+                [i] "s"(__builtin_amdgcn_readfirstlane(min(bc::h1_put_slot(h1), (uint32_t)(K - 1)) * 4u)));
   }
   if (h1 & bc::H1_STORE) {
     const uint32_t o = bc::h1_store_strip(h1);
     const uint64_t base = strip_base(tab_lo, tab_hi, n_in + (o >> 3), o & 7u, strip_len, toff);
     // s_nop 4: the base may come from v_readlane; s_nop 1: one wait state
     // before a VALU may overwrite the data registers of a 16-byte store.
-    EC_SLOT_ASM(K, "s_nop 4\n\tglobal_store_dwordx4 %[off], v[0:3], %[base]\n\ts_nop 1", [off] "v"(voff),
-                [base] "s"(base));
+    asm volatile("s_nop 4\n\tglobal_store_dwordx4 %[off], v[0:3], %[base]\n\ts_nop 1"
+                 :: "{v[0:3]}"(acc), [off] "v"(voff), [base] "s"(base));
   }
-  if (h1 & bc::H1_CLEAR)
-    EC_SLOT_ASM(K, "v_mov_b32_e32 v0, 0\n\tv_mov_b32_e32 v1, 0\n\tv_mov_b32_e32 v2, 0\n\tv_mov_b32_e32 v3, 0", );
+  push_run<K>(W, nq, h0 & bc::H0_SET, SLOT_ARGS);
+  if (h1 & bc::H1_CLEAR) asm volatile(EC_ZERO_ACC : "+{v[0:3]}"(acc));
   return (h1 & bc::H1_HALT) != 0;
 }
 
@@ -490,7 +595,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *__restrict__ prog, uint
                                          uint32_t tab_hi, uint32_t n_in, uint32_t strip_len, uint64_t toff,
                                          SLOT_PARAMS) {
   uint32_t pc = 0;
-  Win A = *reinterpret_cast<const Win *>(prog), B;
+  Win A = load_block(prog, 0), B;
   // Two windows used in turn, so no copy between blocks.
   for (;;) {
     if (run_block<K>(prog, A, pc, B, voff, tab_lo, tab_hi, n_in, strip_len, toff, SLOT_ARGS)) break;
@@ -513,8 +618,10 @@ __global__ void __launch_bounds__(256) slp_exec_kernel(ExecArgs a) {
       tab_hi = (uint32_t)(a.blk[b] >> 32);
     }
   const uint32_t voff = lane * 16u;
-  v4u acc = {0u, 0u, 0u, 0u};
-  v32u g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+  // the slot registers come to life here, after the prologue's temporaries
+  v4u acc;
+  v32u g0, g1, g2, g3, g4, g5;
+  EC_SLOT_INIT(K);
   for (uint32_t tile = wave; tile < a.n_tiles; tile += n_waves) {
     const uint64_t toff = (uint64_t)tile * kTileBytes;
     if (toff + voff < a.strip_len)

@@ -185,15 +185,15 @@ int schedule(const Slp &p, int n_in_strips, int n_out_strips, const SchedOpts &o
     loads_at[std::min(at, loads[i].use)].push_back(i);
   }
   std::vector<bc::Micro> ops;
-  auto micro = [](bc::Kind k, int flags, int slot, int strip, int count) {
-    return bc::Micro{k, (uint8_t)flags, (int16_t)slot, (int16_t)strip, (int16_t)count};
+  auto micro = [](bc::Kind k, int slot, int strip, int count) {
+    return bc::Micro{k, (int16_t)slot, (int16_t)strip, (int16_t)count};
   };
   std::vector<long> pending(K, -1);  // vm op sequence of the last load into a slot
   long issued = 0, completed = -1;
   const long maxq = std::min(opts.max_inflight, bc::kMaxVmcnt);
   auto throttle = [&]() {
     if (issued - 1 - completed >= maxq) {
-      ops.push_back(micro(bc::WAIT, 0, 0, 0, (int)maxq - 1));
+      ops.push_back(micro(bc::WAIT, 0, 0, (int)maxq - 1));
       completed = issued - maxq;
     }
   };
@@ -201,7 +201,7 @@ int schedule(const Slp &p, int n_in_strips, int n_out_strips, const SchedOpts &o
   for (int q = 0; q < (int)pos.size(); ++q) {
     for (int li : loads_at[q]) {
       throttle();
-      ops.push_back(micro(bc::LD, 0, loads[li].slot, loads[li].strip, 0));
+      ops.push_back(micro(bc::LD, loads[li].slot, loads[li].strip, 0));
       pending[loads[li].slot] = issued++;
       ++n_loads;
     }
@@ -209,28 +209,26 @@ int schedule(const Slp &p, int n_in_strips, int n_out_strips, const SchedOpts &o
     if (pos[q].operand >= 0) {
       const int s = read_slot[q];
       if (pending[s] > completed) {
-        ops.push_back(micro(bc::WAIT, 0, 0, 0, (int)(issued - 1 - pending[s])));
+        ops.push_back(micro(bc::WAIT, 0, 0, (int)(issued - 1 - pending[s])));
         completed = pending[s];
       }
-      ops.push_back(micro(bc::OPERAND, 0, s, 0, 0));
+      ops.push_back(micro(bc::PULL, s, 0, 0));
     } else {
       const int ps = put_slot[pos[q].stmt];
-      if (ps >= 0) pending[ps] = -1;
-      if (x.stores.empty()) {
-        ops.push_back(micro(bc::END, bc::kEndPut, ps, 0, 0));
-      } else {
-        for (size_t k = 0; k < x.stores.size(); ++k) {
-          const bool last = k + 1 == x.stores.size();
-          throttle();
-          int fl = bc::kEndStore | (last ? 0 : bc::kEndKeep) | ((last && x.put) ? bc::kEndPut : 0);
-          ops.push_back(micro(bc::END, fl, (last && x.put) ? ps : 0, x.stores[k], 0));
-          ++issued;
-          ++n_stores;
-        }
+      if (ps >= 0) {
+        pending[ps] = -1;
+        ops.push_back(micro(bc::PUT, ps, 0, 0));
       }
+      for (int o : x.stores) {
+        throttle();
+        ops.push_back(micro(bc::STORE, 0, o, 0));
+        ++issued;
+        ++n_stores;
+      }
+      ops.push_back(micro(bc::CLEAR, 0, 0, 0));
     }
   }
-  ops.push_back(micro(bc::HALT, 0, 0, 0, 0));
+  ops.push_back(micro(bc::HALT, 0, 0, 0));
   out.words = bc::pack(ops);
 
   int used = 0;
@@ -252,36 +250,52 @@ std::vector<uint32_t> pack(const std::vector<Micro> &ops) {
   const size_t N = ops.size();
   while (i < N) {
     uint32_t h0 = 0, h1 = 0;
-    std::vector<uint32_t> operands;
-    if (ops[i].kind == LD) {
-      h0 |= H0_LD | ((uint32_t)ops[i].slot << 5) | ((uint32_t)ops[i].strip << 11);
-      ++i;
+    std::vector<uint32_t> pulls, pushes;
+    int stage = 0;  // canonical order: LD WAIT PULL PUT STORE PUSH CLEAR HALT
+    bool set_mode = false;
+    for (; i < N; ++i) {
+      const Micro &m = ops[i];
+      const bool room = pulls.size() + pushes.size() < (size_t)kMaxOperands;
+      if (m.kind == LD && stage < 1) {
+        h0 |= H0_LD | ((uint32_t)m.slot << 9) | ((uint32_t)m.strip << 15);
+        stage = 1;
+      } else if (m.kind == WAIT && stage < 2) {
+        h0 |= H0_WAIT;
+        h1 |= (uint32_t)m.count;
+        stage = 2;
+      } else if (m.kind == PULL && stage <= 2 && room) {
+        pulls.push_back((uint32_t)(4 * m.slot));
+        stage = 2;
+      } else if (m.kind == PUT && stage < 4) {
+        h1 |= H1_PUT | ((uint32_t)m.slot << 7);
+        stage = 4;
+      } else if (m.kind == STORE && stage < 5) {
+        h1 |= H1_STORE | ((uint32_t)m.strip << 14);
+        stage = 5;
+      } else if ((m.kind == PUSH || m.kind == PUSHSET) && stage <= 5 && room &&
+                 (pushes.empty() || set_mode == (m.kind == PUSHSET))) {
+        set_mode = m.kind == PUSHSET;
+        pushes.push_back((uint32_t)(4 * m.slot));
+        stage = 5;
+      } else if (m.kind == CLEAR && stage < 7) {
+        h1 |= H1_CLEAR;
+        stage = 7;
+      } else if (m.kind == HALT && stage < 8) {
+        h1 |= H1_HALT;
+        stage = 8;
+      } else {
+        break;
+      }
     }
-    if (i < N && ops[i].kind == WAIT) {
-      h0 |= H0_WAIT | ((uint32_t)ops[i].count << 23);
-      ++i;
-    }
-    while (i < N && ops[i].kind == OPERAND && (int)operands.size() < kMaxOperands) {
-      operands.push_back((uint32_t)(4 * ops[i].slot));
-      ++i;
-    }
-    if (i < N && ops[i].kind == END) {
-      const Micro &e = ops[i];
-      if (e.flags & kEndPut) h1 |= H1_PUT | ((uint32_t)e.slot << 5);
-      if (e.flags & kEndStore) h1 |= H1_STORE | ((uint32_t)e.strip << 11);
-      if (!(e.flags & kEndKeep)) h1 |= H1_CLEAR;
-      ++i;
-    }
-    if (i < N && ops[i].kind == HALT) {
-      h1 |= H1_HALT;
-      ++i;
-    }
-    h0 |= (uint32_t)operands.size();
-    w.push_back(h0);
-    w.push_back(h1);
-    w.insert(w.end(), operands.begin(), operands.end());
+    h0 |= (uint32_t)pulls.size() | ((uint32_t)pushes.size() << 4) | (set_mode ? H0_SET : 0u);
+    const size_t base = w.size();
+    w.resize(base + kBlockWords, 0u);
+    w[base] = h0;
+    w[base + 1] = h1;
+    for (size_t k = 0; k < pulls.size(); ++k) w[base + 2 + k] = pulls[k];
+    for (size_t k = 0; k < pushes.size(); ++k) w[base + kBlockWords - pushes.size() + k] = pushes[k];
   }
-  w.insert(w.end(), kWindow, 0u);
+  w.resize(w.size() + kBlockWords, 0u);  // read-ahead block after HALT
   return w;
 }
 
@@ -289,28 +303,95 @@ std::vector<uint32_t> pack(const std::vector<Micro> &ops) {
 
 bool validate_bytecode(const std::vector<uint32_t> &w, int slots, int n_in_strips, int n_out_strips) {
   // Walk the blocks exactly as the device does; the device trusts every field.
-  size_t pc = 0;
-  for (;;) {
-    if (pc + bc::kWindow > w.size()) return false;  // device reads a full window
+  if (w.size() % bc::kBlockWords != 0) return false;
+  auto slot_word_ok = [&](uint32_t o) { return (o & ~0xFCu) == 0 && (int)(o >> 2) < slots; };
+  for (size_t pc = 0;; pc += bc::kBlockWords) {
+    if (pc + 2 * bc::kBlockWords > w.size()) return false;  // the device reads one block ahead
     const uint32_t h0 = w[pc], h1 = w[pc + 1];
-    const uint32_t n = h0 & bc::H0_N;
-    if (n > (uint32_t)bc::kMaxOperands) return false;
-    if (h0 >> 29) return false;
-    if ((h0 & bc::H0_LD) && ((int)bc::h0_ld_slot(h0) >= slots || (int)bc::h0_ld_strip(h0) >= n_in_strips))
+    const uint32_t np = bc::h0_np(h0), nq = bc::h0_nq(h0);
+    if (np + nq > (uint32_t)bc::kMaxOperands) return false;
+    if (h0 >> 28) return false;
+    if (h0 & bc::H0_LD) {
+      if ((int)bc::h0_ld_slot(h0) >= slots || (int)bc::h0_ld_strip(h0) >= n_in_strips) return false;
+    } else if (h0 & 0x03FFFE00u) {
       return false;
-    if (!(h0 & bc::H0_LD) && (h0 & 0x003FFFE0u)) return false;
-    if (!(h0 & bc::H0_WAIT) && (h0 >> 23)) return false;
-    if (h1 & ~0x003FFFEFu) return false;
-    if ((h1 & bc::H1_PUT) && (int)bc::h1_put_slot(h1) >= slots) return false;
-    if ((h1 & bc::H1_STORE) && (int)bc::h1_store_strip(h1) >= n_out_strips) return false;
-    for (uint32_t k = 0; k < n; ++k) {
-      const uint32_t o = w[pc + 2 + k];
-      if ((o & ~0xFCu) != 0 || (int)(o >> 2) >= slots) return false;
     }
-    pc += 2 + n;
-    if (h1 & bc::H1_HALT) break;
+    if (!(h0 & bc::H0_WAIT) && bc::h1_wait(h1)) return false;
+    if (h1 >> 27) return false;
+    if (h1 & bc::H1_PUT) {
+      if ((int)bc::h1_put_slot(h1) >= slots) return false;
+    } else if (h1 & 0x1F80u) {
+      return false;
+    }
+    if (h1 & bc::H1_STORE) {
+      if ((int)bc::h1_store_strip(h1) >= n_out_strips) return false;
+    } else if (h1 & 0x01FFC000u) {
+      return false;
+    }
+    for (uint32_t k = 0; k < (uint32_t)bc::kMaxOperands; ++k) {
+      const uint32_t o = w[pc + 2 + k];
+      const bool used = k < np || k >= (uint32_t)bc::kMaxOperands - nq;
+      if (used ? !slot_word_ok(o) : o != 0) return false;
+    }
+    if (h1 & bc::H1_HALT) return pc + 2 * bc::kBlockWords == w.size();
   }
-  return pc + bc::kWindow == w.size();
+}
+
+// ---------------------------------------------------------------- broadcast form
+int schedule_broadcast(const std::vector<Bits> &rows, int n_in_strips, const SchedOpts &opts, SchedResult &out) {
+  const int R = (int)rows.size();
+  const int K = opts.slots;
+  const int Q = K - R;  // ring of prefetch slots for input strips
+  if (Q < 2) return -1;
+  std::vector<int> inputs;
+  std::vector<std::vector<int>> targets;
+  for (int c = 0; c < n_in_strips; ++c) {
+    std::vector<int> t;
+    for (int j = 0; j < R; ++j)
+      if (rows[j].test(c)) t.push_back(j);
+    if (!t.empty()) { inputs.push_back(c); targets.push_back(t); }
+  }
+  const int U = (int)inputs.size();
+  std::vector<bc::Micro> ops;
+  auto m = [](bc::Kind k, int slot, int strip, int count) {
+    return bc::Micro{k, (int16_t)slot, (int16_t)strip, (int16_t)count};
+  };
+  long issued = 0;
+  std::vector<long> seq(U, -1);
+  auto ring = [&](int i) { return R + (i % Q); };
+  // Prefetch the first Q inputs, interleaved with zeroing the accumulators
+  // (acc is 0 at tile start, so PUSHSET writes zeros).
+  int z = 0, pre = 0;
+  while (z < R || pre < std::min(Q, U)) {
+    if (pre < std::min(Q, U)) {
+      ops.push_back(m(bc::LD, ring(pre), inputs[pre], 0));
+      seq[pre++] = issued++;
+    }
+    for (int k = 0; k < bc::kMaxOperands && z < R; ++k) ops.push_back(m(bc::PUSHSET, z++, 0, 0));
+  }
+  for (int i = 0; i < U; ++i) {
+    if (i >= 1 && i - 1 + Q < U) {  // refill the slot input i-1 just left
+      ops.push_back(m(bc::LD, ring(i - 1), inputs[i - 1 + Q], 0));
+      seq[i - 1 + Q] = issued++;
+    }
+    ops.push_back(m(bc::WAIT, 0, 0, (int)(issued - 1 - seq[i])));
+    ops.push_back(m(bc::PULL, ring(i), 0, 0));
+    for (int j : targets[i]) ops.push_back(m(bc::PUSH, j, 0, 0));
+    ops.push_back(m(bc::CLEAR, 0, 0, 0));
+  }
+  for (int j = 0; j < R; ++j) {
+    ops.push_back(m(bc::PULL, j, 0, 0));
+    ops.push_back(m(bc::STORE, 0, j, 0));
+    ops.push_back(m(bc::CLEAR, 0, 0, 0));
+  }
+  ops.push_back(m(bc::HALT, 0, 0, 0));
+  out.words = bc::pack(ops);
+  out.slots_used = R + std::min(Q, U);
+  out.peak_live = out.slots_used;
+  out.n_loads = U;
+  out.n_stores = R;
+  if (!validate_bytecode(out.words, K, n_in_strips, R)) return -2;
+  return 0;
 }
 
 }  // namespace ec
