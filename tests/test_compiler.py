@@ -158,7 +158,7 @@ def test_hoist_option_keeps_semantics():
     gen = E.ec_matrix_cauchy(10, 4)
     rows = oracle_rows(gen, 10, 4)
     for h in (1, 4, 64, 1000):
-        prog = E.ec_compile_slp(10, 4, gen, hoist=h)
+        prog = E.ec_compile_slp(10, 4, gen, hoist=h, slot_budget=32)
         got = simulate(prog.bytecode(), 32, 80, 32)
         assert [got[o] for o in range(32)] == rows
 
