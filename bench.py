@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
     ap.add_argument("--only", choices=["all", "compressed", "plain"], default="all")
     ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = --slots)")
+    ap.add_argument("--batch-stripes", type=int, default=8192, help="stripes in the batched workload (0 = skip)")
+    ap.add_argument("--batch-max-mib", type=int, default=4, help="largest block of the batched workload (MiB)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of Poisson arrivals (0 = skip)")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--sweep", action="store_true",
                     help="time every (level, slot budget) pair on the workload and print one line each")
     return ap.parse_args()
@@ -175,9 +179,60 @@ def main():
     out.update(extra)
     if "copy_ceiling_GB_s" in out:
         out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GB_s"]
+    if args.only == "all" and args.batch_stripes > 0:
+        del data, parity
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(args, stream)
+        torch.cuda.empty_cache()
+    if args.only == "all" and args.serve_seconds > 0:
+        from paper_2108_02692_amd import serve
+        out["serving"] = serve.run(duration_s=args.serve_seconds, seed=7)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_block_mib)
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, stream):
+    """8192 stripes mixing RS(6,3), RS(10,4), RS(12,4), RS(14,4); block sizes
+    log-uniform 4 KiB .. 4 MiB in 512 B steps; 70% encodes, 30% decodes with
+    uniformly drawn erasure sets; one persistent graph launch per step.
+    Inputs are slices of one seeded random pool (read-only, so stripes may
+    share bytes); every output is its own buffer."""
+    import numpy as np
+    import torch
+    from paper_2108_02692_amd import autotune, batching
+
+    specs = batching.mixed_specs(args.batch_stripes, seed=4, hi=args.batch_max_mib << 20)
+    pool_bytes = 4 << 30
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    rng = np.random.default_rng(5)
+    out_total = sum(s.n_out * s.block_bytes for s in specs)
+    out_buf = torch.empty(out_total, dtype=torch.uint8, device="cuda")
+    inputs, outputs, off = [], [], 0
+    for s in specs:
+        hi = (pool_bytes - s.block_bytes) // 4096
+        inputs.append([pool[o:o + s.block_bytes] for o in (rng.integers(0, hi, s.n_in) * 4096).tolist()])
+        outputs.append([out_buf[off + j * s.block_bytes: off + (j + 1) * s.block_bytes] for j in range(s.n_out)])
+        off += s.n_out * s.block_bytes
+    in_bytes = sum(s.n_in * s.block_bytes for s in specs)
+    key = "mix4-%d-%dMiB" % (args.batch_stripes, args.batch_max_mib)
+    best, table = autotune.tune(key, specs, inputs, outputs, stream, retune=args.retune)
+    cache = batching.ProgramCache(level=best["level"], slots=best["slots"])
+    cache.warm({(s.n, s.p, s.erased) for s in specs})
+    batch = batching.build_batch(specs, cache, inputs, outputs, tile_bytes=best["tile_bytes"], stream=stream)
+    ms = autotune.time_batch(batch, stream, steps=max(3, args.steps // 2), warmup=1)
+    res = {"stripes": len(specs), "work_items": batch.n_items, "in_bytes": in_bytes, "out_bytes": out_total,
+           "ms": ms, "GB_s": in_bytes / ms / 1e6, "hbm_frac": (in_bytes + out_total) / ms / 1e6 / HBM_PEAK_GBS,
+           "level": best["level"], "slots": best["slots"], "tile_bytes": best["tile_bytes"],
+           "programs": len(cache), "graph": True}
+    if table:
+        res["autotune"] = table
+    batch.free()
+    del pool, out_buf, inputs, outputs
+    return res
 
 
 def cpu_baseline(block_mib: int):

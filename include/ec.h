@@ -175,15 +175,33 @@ typedef struct {
 
 /* Prepare a launch over n_stripes stripes: uploads the stripe descriptors
  * and program bytecode to the device (synchronously, on `stream`).  The
- * stripes' buffers must stay valid for every later ec_batch_launch.
- * tile_bytes: bytes per strip handled by one work item (multiple of 1024;
- * 0 = default).  Programs in one batch must share one slot budget. */
+ * stripes' buffers and programs must stay valid for every later launch.
+ * tile_bytes: bytes per strip one work item covers (a multiple of 1024, the
+ * bytes of a strip one wave handles per tile; 0 = 1024).  Programs in one
+ * batch must share one slot budget (EC_ERR_UNSUPPORTED otherwise). */
 ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
                          ec_batch **out);
 
-/* Run the batch: one persistent kernel whose waves take work items from a
- * device queue.  Capturable into a HIP graph (no allocation, no memset). */
+/* Run the batch: one launch of the HIP graph built by ec_batch_build (a
+ * one-thread kernel resetting the work counter, then the persistent
+ * executor whose waves take (stripe, tile) work items from that counter).
+ * Launches of one batch must not overlap (they share the counter). */
 ec_status ec_batch_launch(ec_batch *batch, ec_stream stream);
+
+/* The same two kernels enqueued directly on `stream` instead of as a graph:
+ * for callers that capture their own graphs (no allocation, no memset). */
+ec_status ec_batch_enqueue(ec_batch *batch, ec_stream stream);
+
+/* A reusable batch for serving loops: ec_batch_create allocates an empty
+ * batch; ec_batch_set fills it for a new set of stripes, staging the tables
+ * in pinned host memory and enqueueing their copies on `stream` without
+ * waiting (device buffers grow when needed and are never freed before
+ * ec_batch_free).  The previous launch of the batch must have completed
+ * before ec_batch_set is called again.  Run it with ec_batch_enqueue on the
+ * same stream.  Same argument rules and errors as ec_batch_build. */
+ec_status ec_batch_create(ec_batch **out);
+ec_status ec_batch_set(ec_batch *batch, const ec_stripe *stripes, int n_stripes, size_t tile_bytes,
+                       ec_stream stream);
 
 /* Number of work items and total input/output bytes of a batch. */
 ec_status ec_batch_query(const ec_batch *batch, size_t *n_items, size_t *in_bytes, size_t *out_bytes);

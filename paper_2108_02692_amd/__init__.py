@@ -85,13 +85,16 @@ def lib():
         L.ec_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.ec_batch_build.argtypes = [ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.ec_batch_launch.argtypes = [vp, vp]
+        L.ec_batch_enqueue.argtypes = [vp, vp]
+        L.ec_batch_create.argtypes = [ctypes.POINTER(vp)]
+        L.ec_batch_set.argtypes = [vp, ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp]
         L.ec_batch_query.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                      ctypes.POINTER(ctypes.c_size_t)]
         L.ec_batch_free.argtypes = [vp]
         L.ec_batch_free.restype = None
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
                      "ec_encode", "ec_decode", "ec_program_export", "ec_program_bytecode", "ec_batch_build", "ec_device_copy",
-                     "ec_batch_launch", "ec_batch_query"):
+                     "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -241,16 +244,40 @@ def ec_device_copy(dst, src, nbytes: int, stream=None):
 class Batch:
     """Owner of an ``ec_batch`` (many stripes, one persistent launch)."""
 
-    def __init__(self, handle: int, keepalive):
+    def __init__(self, handle: int, keepalive=None):
         self._h = ctypes.c_void_p(handle)
         self._keep = keepalive
+        self._query()
+
+    def _query(self):
         n_items, nin, nout = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         _check(lib().ec_batch_query(self._h, ctypes.byref(n_items), ctypes.byref(nin), ctypes.byref(nout)),
                "ec_batch_query")
         self.n_items, self.in_bytes, self.out_bytes = n_items.value, nin.value, nout.value
 
+    @classmethod
+    def create(cls):
+        """An empty reusable batch (see ``set``)."""
+        h = ctypes.c_void_p()
+        _check(lib().ec_batch_create(ctypes.byref(h)), "ec_batch_create")
+        return cls(h.value)
+
+    def set(self, stripes, tile_bytes: int = 0, stream=None):
+        """Refill with ``stripes`` ((Program, inputs, outputs, block_bytes));
+        asynchronous on ``stream``; the previous launch must have finished."""
+        arr, keep = _stripe_array(stripes)
+        _check(lib().ec_batch_set(self._h, arr, len(keep) // 3, tile_bytes, _stream_handle(stream)),
+               "ec_batch_set")
+        self._keep = keep
+        self._query()
+
     def launch(self, stream=None):
+        """One launch of the batch's HIP graph (reset + persistent kernel)."""
         _check(lib().ec_batch_launch(self._h, _stream_handle(stream)), "ec_batch_launch")
+
+    def enqueue(self, stream=None):
+        """The same kernels enqueued directly (for callers capturing graphs)."""
+        _check(lib().ec_batch_enqueue(self._h, _stream_handle(stream)), "ec_batch_enqueue")
 
     def free(self):
         if self._h is not None and self._h.value:
@@ -264,8 +291,7 @@ class Batch:
             pass
 
 
-def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
-    """``stripes``: iterable of (Program, inputs, outputs, block_bytes)."""
+def _stripe_array(stripes):
     stripes = list(stripes)
     arr = (Stripe * max(1, len(stripes)))()
     keep = []
@@ -276,7 +302,14 @@ def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
         arr[i].in_ = ctypes.cast(ia, ctypes.POINTER(ctypes.c_void_p))
         arr[i].out = ctypes.cast(oa, ctypes.POINTER(ctypes.c_void_p))
         arr[i].block_bytes = bb
+    return arr, keep
+
+
+def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
+    """``stripes``: iterable of (Program, inputs, outputs, block_bytes).
+    Uploads the tables (waiting on ``stream``) and captures a HIP graph."""
+    arr, keep = _stripe_array(stripes)
     h = ctypes.c_void_p()
-    _check(lib().ec_batch_build(arr, len(stripes), tile_bytes, _stream_handle(stream), ctypes.byref(h)),
+    _check(lib().ec_batch_build(arr, len(keep) // 3, tile_bytes, _stream_handle(stream), ctypes.byref(h)),
            "ec_batch_build")
     return Batch(h.value, keep)

@@ -1,14 +1,222 @@
-// batch.cpp -- multi-stripe launches (filled in with the persistent kernel).
+// batch.cpp -- many stripes in one persistent launch.
+//
+// A batch is a table of stripe descriptors and a list of work items
+// (stripe, first tile), uploaded once.  A launch resets the work counter with
+// a one-thread kernel and starts the persistent executor, whose waves pull
+// items until the list is exhausted; both launches are captured into a HIP
+// graph at build time, so a launch is one graph launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <new>
+#include <vector>
+
 #include "../../include/ec.h"
+#include "exec.hpp"
+#include "program.hpp"
+
+using namespace ec;
+
+struct ec_batch {
+  int device = 0;
+  int slots = 0;
+  int grid = 0;
+  size_t n_items = 0, in_bytes = 0, out_bytes = 0;
+  // device tables and their pinned host staging, grown on demand, never
+  // shrunk (so refilling a batch in a serving loop allocates nothing)
+  StripeDesc *d_desc = nullptr, *h_desc = nullptr;
+  uint32_t *d_items = nullptr, *h_items = nullptr;
+  size_t cap_desc = 0, cap_items = 0;
+  uint32_t *d_counter = nullptr;
+  BatchArgs args{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  ~ec_batch() {
+    int cur = 0;
+    const bool swap = hipGetDevice(&cur) == hipSuccess && cur != device && hipSetDevice(device) == hipSuccess;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_desc) (void)hipFree(d_desc);
+    if (d_items) (void)hipFree(d_items);
+    if (d_counter) (void)hipFree(d_counter);
+    if (h_desc) (void)hipHostFree(h_desc);
+    if (h_items) (void)hipHostFree(h_items);
+    if (swap) (void)hipSetDevice(cur);
+  }
+};
+
+namespace {
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Waves per SIMD the executor reaches for a slot budget (VGPRs per lane:
+// 4 + 4K + the kernel's own registers, out of 512).
+int waves_per_simd(int slots) { return slots <= 16 ? 6 : slots <= 24 ? 4 : slots <= 32 ? 3 : 2; }
+
+}  // namespace
 
 extern "C" {
 
-ec_status ec_batch_build(const ec_stripe *, int, size_t, ec_stream, ec_batch **out) {
-  if (out) *out = nullptr;
-  return EC_ERR_UNSUPPORTED;
+ec_status ec_batch_create(ec_batch **out) {
+  if (!out) return EC_ERR_ARG;
+  *out = nullptr;
+  std::unique_ptr<ec_batch> b(new (std::nothrow) ec_batch);
+  if (!b) return EC_ERR_NOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) return EC_ERR_DEVICE;
+  if (hipMalloc((void **)&b->d_counter, 256) != hipSuccess) return EC_ERR_NOMEM;
+  *out = b.release();
+  return EC_OK;
 }
-ec_status ec_batch_launch(ec_batch *, ec_stream) { return EC_ERR_UNSUPPORTED; }
-ec_status ec_batch_query(const ec_batch *, size_t *, size_t *, size_t *) { return EC_ERR_UNSUPPORTED; }
-void ec_batch_free(ec_batch *) {}
+
+ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream) {
+  if (!b || !stripes || n_stripes <= 0) return EC_ERR_ARG;
+  if (tile_bytes == 0) tile_bytes = kTileBytes;
+  if (tile_bytes % kTileBytes != 0 || tile_bytes / kTileBytes > 4096) return EC_ERR_UNSUPPORTED;
+  const uint32_t tiles_per_item = (uint32_t)(tile_bytes / kTileBytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return EC_ERR_DEVICE;
+  std::vector<StripeDesc> desc((size_t)n_stripes);
+  std::vector<uint32_t> items;
+  int slots = 0;
+  size_t in_bytes = 0, out_bytes = 0;
+  for (int s = 0; s < n_stripes; ++s) {
+    const ec_stripe &st = stripes[s];
+    const ec_program *prog = st.prog;
+    if (!prog || !st.in || !st.out) return EC_ERR_ARG;
+    if (st.block_bytes == 0 || st.block_bytes % 128 != 0) return EC_ERR_ALIGN;
+    if (st.block_bytes / 8 > 0x1FFFFFFFull) return EC_ERR_UNSUPPORTED;
+    if (s == 0) slots = prog->slots;
+    else if (prog->slots != slots) return EC_ERR_UNSUPPORTED;  // one kernel instance per launch
+    const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+    StripeDesc &d = desc[s];
+    for (int i = 0; i < n_in; ++i) {
+      if (!st.in[i]) return EC_ERR_ARG;
+      if (!aligned16(st.in[i])) return EC_ERR_ALIGN;
+      d.blk[i] = (uint64_t)(uintptr_t)st.in[i];
+    }
+    for (int j = 0; j < n_out; ++j) {
+      if (!st.out[j]) return EC_ERR_ARG;
+      if (!aligned16(st.out[j])) return EC_ERR_ALIGN;
+      const uintptr_t a = (uintptr_t)st.out[j];
+      for (int i = 0; i < n_in; ++i) {
+        const uintptr_t c = (uintptr_t)st.in[i];
+        if (a < c + st.block_bytes && c < a + st.block_bytes) return EC_ERR_ARG;
+      }
+      d.blk[n_in + j] = (uint64_t)a;
+    }
+    ec_status ws = EC_OK;
+    d.prog = const_cast<ec_program *>(prog)->device_words(&ws);
+    if (!d.prog) return ws;
+    d.n_in = (uint32_t)n_in;
+    d.strip_len = (uint32_t)(st.block_bytes / 8);
+    const uint32_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
+    for (uint32_t t = 0; t < n_tiles; t += tiles_per_item) {
+      items.push_back((uint32_t)s);
+      items.push_back(t);
+    }
+    in_bytes += (size_t)n_in * st.block_bytes;
+    out_bytes += (size_t)n_out * st.block_bytes;
+  }
+  if (items.size() / 2 > 0xFFFFFFFFull) return EC_ERR_UNSUPPORTED;
+  // grow device tables and pinned staging when needed
+  if (desc.size() > b->cap_desc) {
+    const size_t cap = std::max(desc.size(), 2 * b->cap_desc);
+    StripeDesc *d = nullptr, *h = nullptr;
+    if (hipMalloc((void **)&d, cap * sizeof(StripeDesc)) != hipSuccess) return EC_ERR_NOMEM;
+    if (hipHostMalloc((void **)&h, cap * sizeof(StripeDesc), hipHostMallocDefault) != hipSuccess) {
+      (void)hipFree(d);
+      return EC_ERR_NOMEM;
+    }
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    b->d_desc = d;
+    b->h_desc = h;
+    b->cap_desc = cap;
+  }
+  if (items.size() > b->cap_items) {
+    const size_t cap = std::max(items.size(), 2 * b->cap_items);
+    uint32_t *d = nullptr, *h = nullptr;
+    if (hipMalloc((void **)&d, cap * sizeof(uint32_t)) != hipSuccess) return EC_ERR_NOMEM;
+    if (hipHostMalloc((void **)&h, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      (void)hipFree(d);
+      return EC_ERR_NOMEM;
+    }
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->h_items) (void)hipHostFree(b->h_items);
+    b->d_items = d;
+    b->h_items = h;
+    b->cap_items = cap;
+  }
+  std::copy(desc.begin(), desc.end(), b->h_desc);
+  std::copy(items.begin(), items.end(), b->h_items);
+  const hipStream_t hs = (hipStream_t)stream;
+  if (hipMemcpyAsync(b->d_desc, b->h_desc, desc.size() * sizeof(StripeDesc), hipMemcpyHostToDevice, hs) !=
+          hipSuccess ||
+      hipMemcpyAsync(b->d_items, b->h_items, items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs) !=
+          hipSuccess)
+    return EC_ERR_DEVICE;
+  b->slots = slots;
+  b->n_items = items.size() / 2;
+  b->in_bytes = in_bytes;
+  b->out_bytes = out_bytes;
+  b->args.stripes = b->d_desc;
+  b->args.items = b->d_items;
+  b->args.n_items = (uint32_t)b->n_items;
+  b->args.counter = b->d_counter;
+  b->args.tiles_per_item = tiles_per_item;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return EC_ERR_DEVICE;
+  b->grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)prop.multiProcessorCount * waves_per_simd(b->slots),
+                                                      (b->n_items + 3) / 4));
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return EC_OK;
+}
+
+ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
+                         ec_batch **out) {
+  if (!out) return EC_ERR_ARG;
+  *out = nullptr;
+  ec_batch *raw = nullptr;
+  ec_status st = ec_batch_create(&raw);
+  if (st != EC_OK) return st;
+  std::unique_ptr<ec_batch> b(raw);
+  st = ec_batch_set(b.get(), stripes, n_stripes, tile_bytes, stream);
+  if (st != EC_OK) return st;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return EC_ERR_DEVICE;
+  // Capture reset + persistent kernel into a graph on a private stream.
+  hipStream_t cap;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return EC_ERR_DEVICE;
+  bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+  ok = ok && batch_launch(b->slots, b->args, b->grid, cap) == 0;
+  ok = (hipStreamEndCapture(cap, &b->graph) == hipSuccess) && ok;
+  ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipStreamDestroy(cap);
+  if (!ok) return EC_ERR_DEVICE;
+  *out = b.release();
+  return EC_OK;
+}
+
+ec_status ec_batch_launch(ec_batch *batch, ec_stream stream) {
+  if (!batch || !batch->exec) return EC_ERR_ARG;
+  return hipGraphLaunch(batch->exec, (hipStream_t)stream) == hipSuccess ? EC_OK : EC_ERR_DEVICE;
+}
+
+ec_status ec_batch_enqueue(ec_batch *batch, ec_stream stream) {
+  if (!batch || batch->n_items == 0) return EC_ERR_ARG;
+  return batch_launch(batch->slots, batch->args, batch->grid, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
+}
+
+ec_status ec_batch_query(const ec_batch *batch, size_t *n_items, size_t *in_bytes, size_t *out_bytes) {
+  if (!batch) return EC_ERR_ARG;
+  if (n_items) *n_items = batch->n_items;
+  if (in_bytes) *in_bytes = batch->in_bytes;
+  if (out_bytes) *out_bytes = batch->out_bytes;
+  return EC_OK;
+}
+
+void ec_batch_free(ec_batch *batch) { delete batch; }
 
 }  // extern "C"

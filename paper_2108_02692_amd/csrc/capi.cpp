@@ -15,52 +15,9 @@
 #include "gf.hpp"
 #include "sched.hpp"
 #include "slp.hpp"
+#include "program.hpp"
 
 using namespace ec;
-
-struct ec_program {
-  int n = 0, p = 0;
-  bool decode = false;
-  int level = EC_LEVEL_CO_FU_SCHED;
-  int slots = 32;
-  std::vector<int> in_blocks, out_blocks;
-  Slp plain, co, fu, sched;  // pipeline stages (co/fu/sched empty for PLAIN)
-  const Slp *final_stage = nullptr;
-  Slp exec;                  // the program the executor runs (fitted to the slot budget)
-  SchedResult code;
-  ec_program_info info{};
-  std::mutex mu;
-  std::map<int, uint32_t *> dev_words;  // device -> bytecode copy
-
-  ~ec_program() {
-    for (auto &kv : dev_words) {
-      int cur = 0;
-      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
-        (void)hipFree(kv.second);
-        (void)hipSetDevice(cur);
-      }
-    }
-  }
-
-  // Device copy of the bytecode for the current device (uploaded once).
-  const uint32_t *device_words(ec_status *st) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) { *st = EC_ERR_DEVICE; return nullptr; }
-    std::lock_guard<std::mutex> g(mu);
-    auto it = dev_words.find(dev);
-    if (it != dev_words.end()) return it->second;
-    uint32_t *d = nullptr;
-    const size_t bytes = code.words.size() * sizeof(uint32_t);
-    if (hipMalloc((void **)&d, bytes) != hipSuccess) { *st = EC_ERR_NOMEM; return nullptr; }
-    if (hipMemcpy(d, code.words.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-      (void)hipFree(d);
-      *st = EC_ERR_DEVICE;
-      return nullptr;
-    }
-    dev_words[dev] = d;
-    return d;
-  }
-};
 
 namespace {
 

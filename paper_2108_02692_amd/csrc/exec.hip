@@ -629,6 +629,56 @@ __global__ void __launch_bounds__(256) slp_exec_kernel(ExecArgs a) {
   }
 }
 
+// ---- batched execution: one persistent launch over many stripes
+// Waves take (stripe, tile) work items from a device counter; each item runs
+// its stripe's program on one tile.  Items and descriptors are read-only for
+// the launch and are read through the scalar cache.
+typedef const __attribute__((address_space(4))) StripeDesc *ConstDescPtr;
+typedef const __attribute__((address_space(4))) uint32_t *ConstU32Ptr;
+
+__global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
+
+template <int K>
+__global__ void __launch_bounds__(256) slp_batch_kernel(BatchArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t voff = lane * 16u;
+  v4u acc;
+  v32u g0, g1, g2, g3, g4, g5;
+  EC_SLOT_INIT(K);
+  for (;;) {
+    uint32_t it = 0;
+    if (lane == 0) it = atomicAdd(a.counter, 1u);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= a.n_items) break;
+    const uint32_t stripe = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it];
+    const uint32_t tile = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it + 1];
+    ConstDescPtr d = (ConstDescPtr)(uintptr_t)(a.stripes + stripe);
+    const uint32_t *prog = d->prog;
+    const uint32_t n_in = d->n_in, strip_len = d->strip_len;
+    // lane b holds the pointer of block b of this stripe
+    const uint64_t p = lane < (uint32_t)kMaxBlocks ? a.stripes[stripe].blk[lane] : 0ull;
+    const uint32_t tab_lo = (uint32_t)p, tab_hi = (uint32_t)(p >> 32);
+    for (uint32_t t = 0; t < a.tiles_per_item; ++t) {
+      const uint64_t toff = (uint64_t)(tile + t) * kTileBytes;
+      if (toff >= strip_len) break;
+      if (toff + voff < strip_len) run_tile<K>(prog, voff, tab_lo, tab_hi, n_in, strip_len, toff, SLOT_ARGS);
+    }
+  }
+}
+
+int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.counter);
+  switch (slots) {
+    case 16: hipLaunchKernelGGL(slp_batch_kernel<16>, dim3(grid), dim3(256), 0, stream, a); break;
+    case 24: hipLaunchKernelGGL(slp_batch_kernel<24>, dim3(grid), dim3(256), 0, stream, a); break;
+    case 32: hipLaunchKernelGGL(slp_batch_kernel<32>, dim3(grid), dim3(256), 0, stream, a); break;
+    case 40: hipLaunchKernelGGL(slp_batch_kernel<40>, dim3(grid), dim3(256), 0, stream, a); break;
+    case 48: hipLaunchKernelGGL(slp_batch_kernel<48>, dim3(grid), dim3(256), 0, stream, a); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // Plain device copy (16 B per lane, grid-stride): the bandwidth ceiling the
 // executor is compared with, and the calibration kernel for byte counters.
 __global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,

@@ -18,6 +18,26 @@ struct ExecArgs {
   uint64_t strip_len;        // bytes per strip (block_bytes / 8), multiple of 16
 };
 
+// One stripe of a batched launch (device memory, read-only during a launch).
+struct StripeDesc {
+  uint64_t blk[kMaxBlocks];  // input block pointers, then output block pointers
+  const uint32_t *prog;      // the stripe's device bytecode
+  uint32_t n_in;             // input blocks
+  uint32_t strip_len;        // bytes per strip
+};
+
+// Arguments of the persistent batched kernel.
+struct BatchArgs {
+  const StripeDesc *stripes;
+  const uint32_t *items;  // 2 words per work item: stripe index, tile index
+  uint32_t n_items;
+  uint32_t tiles_per_item;  // consecutive tiles one work item covers
+  uint32_t *counter;        // next work item; reset to 0 by the launch itself
+};
+
+// Reset the work counter and launch the persistent kernel for `slots`.
+int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream);
+
 // Launch the executor instance for `slots` register slots; 0 on success.
 int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t stream);
 

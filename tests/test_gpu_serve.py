@@ -1,0 +1,66 @@
+"""Serving loop on the GPU: every request served inside a mixed, continuously
+batched stream gives the same bytes as the same request served alone, and
+both equal the oracle's product of the request's matrix with its inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_02692_amd import serve as SV
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def outputs_of(server, reqs):
+    return [[server.arena[r.out_off + j * r.block_bytes: r.out_off + (j + 1) * r.block_bytes].cpu().numpy()
+             for j in range(r.n_out)] for r in reqs]
+
+
+def expected(server, req, pool_h, pool_ptr):
+    G = np.array(server.cache.generator(req.n, req.p), dtype=np.uint8)
+    ins = [pool_h[x - pool_ptr: x - pool_ptr + req.block_bytes] for x in req.inputs]
+    if req.erased:
+        D, surv = oracle.decode_matrix(G, req.n, req.p, list(req.erased))
+        assert surv == server.cache.get(req.n, req.p, req.erased).in_blocks
+    else:
+        D = G[req.n:]
+    return oracle.apply(D, [np.ascontiguousarray(b) for b in ins])
+
+
+def test_mix_equals_alone_equals_oracle():
+    pool_bytes = 8 << 20
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    pool_h = pool.cpu().numpy()
+    reqs = SV.make_requests(0.004, 20000.0, seed=5, pool_ptr=pool.data_ptr(), pool_bytes=pool_bytes,
+                            hi=1 << 20)
+    assert len(reqs) > 40
+    # A budget far below the total forces admission back-pressure and many
+    # batches in flight; small batches interleave codecs and sizes.
+    server = SV.Server(budget_bytes=16 << 20, n_slots=3, max_batch=7, warm=False)
+    for r in reqs:
+        server.cache.get(r.n, r.p, r.erased)
+    for r in reqs:
+        r.arrival = 0.0
+    mixed = {}
+
+    def grab(done):
+        mixed.update({r.rid: o for r, o in zip(done, outputs_of(server, done))})
+    server.serve(reqs, realtime=False, on_done=grab)
+    torch.cuda.synchronize()
+    assert all(r.done >= 0 for r in reqs) and len(mixed) == len(reqs)
+    assert server.batches >= len(reqs) // 7 and server.used == 0
+    mixed = [mixed[r.rid] for r in reqs]
+    alone = []
+    for r in reqs:
+        server.serve([r], realtime=False)
+        torch.cuda.synchronize()
+        alone += outputs_of(server, [r])
+    for k, r in enumerate(reqs):
+        for j in range(r.n_out):
+            assert np.array_equal(mixed[k][j], alone[k][j]), "request %d output %d" % (k, j)
+    for k in range(0, len(reqs), 5):
+        want = expected(server, reqs[k], pool_h, pool.data_ptr())
+        for j in range(reqs[k].n_out):
+            assert np.array_equal(alone[k][j], want[j]), "oracle: request %d output %d" % (k, j)
