@@ -62,6 +62,10 @@ def time_launches(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps  # ms per launch
 
 
+def log(msg):
+    print("bench.py: %s" % msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -107,11 +111,13 @@ def main():
                                   "loads": pr.info["n_loads"], "blocks": pr.info["n_words"] // 16 - 1}), flush=True)
         return
 
+    log("compiled (compressed %.0f ms)" % compile_ms)
     res = {}
     if args.only in ("all", "compressed"):
         res["compressed"] = measure(comp, data, parity)
     if args.only in ("all", "plain"):
         res["plain"] = measure(plain, data, parity)
+    log("encode timed: %s" % res)
     extra = {}
     if args.only == "all":
         # decode of the worst 4-erasure set of data blocks (4 data blocks lost)
@@ -182,13 +188,18 @@ def main():
     if args.only == "all" and args.batch_stripes > 0:
         del data, parity
         torch.cuda.empty_cache()
+        log("batched ...")
         out["batched"] = bench_batched(args, stream)
+        log("batched: %.3f ms" % out["batched"]["ms"])
         torch.cuda.empty_cache()
     if args.only == "all" and args.serve_seconds > 0:
         from paper_2108_02692_amd import serve
+        log("serving ...")
         out["serving"] = serve.run(duration_s=args.serve_seconds, seed=7)
+        log("serving: p50 %.3f ms p99 %.3f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]))
         torch.cuda.empty_cache()
     if not args.no_cpu:
+        log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_block_mib)
     print(json.dumps(out), flush=True)
 
@@ -219,7 +230,8 @@ def bench_batched(args, stream):
         off += s.n_out * s.block_bytes
     in_bytes = sum(s.n_in * s.block_bytes for s in specs)
     key = "mix4-%d-%dMiB" % (args.batch_stripes, args.batch_max_mib)
-    best, table = autotune.tune(key, specs, inputs, outputs, stream, retune=args.retune)
+    best, table = autotune.tune(key, specs, inputs, outputs, stream, retune=args.retune,
+                                log=lambda r: log("autotune %s" % r))
     cache = batching.ProgramCache(level=best["level"], slots=best["slots"])
     cache.warm({(s.n, s.p, s.erased) for s in specs})
     batch = batching.build_batch(specs, cache, inputs, outputs, tile_bytes=best["tile_bytes"], stream=stream)
