@@ -103,12 +103,13 @@ def main():
     plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots or args.slots)
     if args.sweep:
         for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
-            for K in (16, 24, 32, 40, 48):
+            for K in (24, 32, 36, 38, 40, 44, 48):
                 pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K)
                 ms = measure(pr, data, parity)
                 print(json.dumps({"sweep": True, "level": level, "slots": K, "ms": ms, "GB_s": in_bytes / ms / 1e6,
                                   "hbm_frac": moved / ms / 1e6 / HBM_PEAK_GBS, "n_xor2": pr.info["n_xor2"],
-                                  "loads": pr.info["n_loads"], "blocks": pr.info["n_words"] // 16 - 1}), flush=True)
+                                  "ops": pr.info["n_ops"], "records": pr.info["n_records"],
+                                  "ring": pr.info["ring"], "open": pr.info["peak_open"]}), flush=True)
         return
 
     log("compiled (compressed %.0f ms)" % compile_ms)
@@ -171,7 +172,8 @@ def main():
             "slots": info["slots"],
             "n_xor2": info["n_xor2"],
             "plain_xor2": info["plain_xor2"],
-            "loads_per_tile": info["n_loads"],
+            "ops_per_tile": info["n_ops"],
+            "records_per_tile": info["n_records"],
             "compile_ms": compile_ms,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -180,7 +182,8 @@ def main():
     if "plain" in res and head == "compressed":
         pms = res["plain"]
         out["plain"] = {"ms": pms, "GB_s": in_bytes / pms / 1e6, "hbm_frac": moved / pms / 1e6 / HBM_PEAK_GBS,
-                        "n_xor2": plain.info["n_xor2"], "loads_per_tile": plain.info["n_loads"]}
+                        "n_xor2": plain.info["n_xor2"], "ops_per_tile": plain.info["n_ops"],
+                        "records_per_tile": plain.info["n_records"], "slots": plain.info["slots"]}
         out["compressed_vs_plain"] = pms / ms
     out.update(extra)
     if "copy_ceiling_GB_s" in out:

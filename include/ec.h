@@ -4,11 +4,17 @@
  *
  * Method: Uezato, "Accelerating XOR-based Erasure Coding using Program
  * Optimization Techniques" (SC'21).  A coding matrix is expanded into a GF(2)
- * bitmatrix (Sec. 1), turned into an XOR straight-line program (Sec. 2, 4.1),
- * compressed by XorRePair (Sec. 4.3-4.4), fused into multi-input XORs
- * (Sec. 5.2), scheduled by a DFS post-order (Sec. 6.6) and then allocated to
- * a bounded set of GPU register slots and emitted as device bytecode that a
- * HIP kernel runs over every tile of every strip.
+ * bitmatrix (Sec. 1) and turned into an XOR straight-line program (Sec. 2,
+ * 4.1), compressed by XorRePair (Sec. 4.3-4.4) and fused into multi-input
+ * XORs (Sec. 5.2).  For the GPU the compression runs on column blocks of the
+ * bitmatrix (one data block each by default), so that the temporaries a
+ * block needs fit in registers, and the program runs in push form: every
+ * value (an input strip or a finished temporary) is brought into an
+ * accumulator once and XORed into each register slot that consumes it;
+ * output rows and open temporaries live in register slots, never in memory.
+ * The slot schedule plays the part of the paper's cache pebbling (Sec. 6).
+ * A HIP kernel interprets the resulting records over every tile of every
+ * strip.
  *
  * Conventions shared by every entry point:
  *  - Status codes only; nothing throws across the ABI.
@@ -55,23 +61,25 @@ typedef enum {
 
 /* Optimisation level of a compiled program (the stages of Sec. 7.5). */
 enum {
-  EC_LEVEL_PLAIN = 0,        /* one multi-input XOR per bitmatrix row (plain bitmatrix SLP) */
-  EC_LEVEL_CO = 1,           /* XorRePair-compressed, binary XORs (Sec. 4.4) */
+  EC_LEVEL_PLAIN = 0,        /* the plain bitmatrix SLP: every strip XORed into each row it feeds */
+  EC_LEVEL_CO = 1,           /* column blocks compressed by XorRePair, binary XORs (Sec. 4.4) */
   EC_LEVEL_CO_FU = 2,        /* compressed then fused (Sec. 5.2) */
-  EC_LEVEL_CO_FU_SCHED = 3   /* compressed, fused, DFS-scheduled (Sec. 6.6); default */
+  EC_LEVEL_CO_FU_SCHED = 3   /* compressed, fused, strips ordered to keep few temporaries open
+                                (the register counterpart of Sec. 6); default */
 };
 
 /* Compression algorithm for levels >= EC_LEVEL_CO. */
 enum { EC_COMPRESS_XORREPAIR = 0, EC_COMPRESS_REPAIR = 1 };
 
 typedef struct {
-  uint32_t level;       /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
-  uint32_t slot_budget; /* register slots per lane for the executor; supported: 16, 24, 32,
-                           40, 48; 0 = default: for the plain level the smallest budget
-                           leaving 8 prefetch slots beside the output rows, else 48 */
-  uint32_t compress;    /* EC_COMPRESS_*; default XorRePair */
-  uint32_t hoist;       /* max distance (in program ops) a strip load is issued ahead
-                           of its first use; 0 = default */
+  uint32_t level;        /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
+  uint32_t slot_budget;  /* register slots per lane (16 B each); supported: 24, 32, 36, 38, 40,
+                            44, 48; 0 = default: the smallest supported budget that holds
+                            all output rows (one pass over the inputs), the open
+                            temporaries and a ring of 6 strip loads (48 if none does) */
+  uint32_t compress;     /* EC_COMPRESS_*; default XorRePair */
+  uint32_t block_strips; /* width in strips of the column blocks compressed separately
+                            (levels >= CO); 0 = 8, one data block; 8*n = the whole matrix */
 } ec_compile_opts;
 
 typedef struct {
@@ -83,10 +91,14 @@ typedef struct {
   uint32_t n_mem;       /* #M: sum over statements of (arity + 1) (Sec. 5.1) */
   uint32_t nvar;        /* variables of the optimised SLP (Sec. 4.1; pebbles after Sec. 6.6) */
   uint32_t plain_xor2;  /* #xor of the plain bitmatrix program (ones - rows) */
-  uint32_t slots;       /* register slots used by the executor (incl. the zero slot) */
-  uint32_t peak_live;   /* peak number of slots holding live values */
-  uint32_t n_loads;     /* strip loads per tile (>= inputs used; extra are reloads) */
+  uint32_t slots;       /* register slot budget the program was scheduled for */
+  uint32_t peak_open;   /* temporaries open at once (slots beside the rows and the ring) */
+  uint32_t ring;        /* strip loads in flight ahead of their use */
+  uint32_t passes;      /* passes over the inputs per tile (1 unless the rows exceed the slots) */
+  uint32_t n_loads;     /* strip loads per tile (inputs used, times passes) */
   uint32_t n_stores;    /* strip stores per tile (= 8 * n_out) */
+  uint32_t n_records;   /* executor records per tile */
+  uint32_t n_ops;       /* slot XORs per tile (the executor's unit of work) */
   uint32_t n_words;     /* bytecode words */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
@@ -110,6 +122,7 @@ ec_status ec_matrix_vandermonde(int n, int p, uint8_t *gen);
  * erased block, data or parity (Sec. 1: the surviving rows form M and
  * M^-1 recovers the data).  Needs 1 <= n, 0 <= p, n + p <= 32 (the
  * executor's block table).  Host-only: needs no GPU.  Thread-safe.
+ * block_strips must be 0 or 1..8n.
  * Errors: EC_ERR_ARG (also for a duplicate or out-of-range erased index),
  * EC_ERR_TOO_MANY_ERASURES (n_erased > p), EC_ERR_SINGULAR, EC_ERR_CAPACITY,
  * EC_ERR_UNSUPPORTED (level / slot budget not supported), EC_ERR_NOMEM. */
@@ -142,8 +155,8 @@ enum {
   EC_STAGE_CO = 1,    /* after (Xor)RePair */
   EC_STAGE_FU = 2,    /* after XOR fusion */
   EC_STAGE_SCHED = 3, /* after DFS scheduling */
-  EC_STAGE_EXEC = 4   /* the program the executor runs: the level's last stage, with
-                         temporaries unfolded until its live values fit the slot budget */
+  EC_STAGE_EXEC = 4   /* the program the executor runs, in push form: its temporaries in
+                         completion order, then one statement per output row */
 };
 
 /* Export one stage as a flat int32 array:
@@ -151,7 +164,10 @@ enum {
  * Terms: t >= 0 is a variable; t == -1 is the zero array; t <= -2 is input
  * strip c = -t - 2 (strip c of input argument c / 8).  Output j*8+r is strip
  * r of output argument j.  *len receives the needed length; nothing is
- * written beyond cap.  Stages CO/FU/SCHED exist for levels >= CO. */
+ * written beyond cap.  Stages PLAIN/CO/FU/SCHED are the paper's whole-matrix
+ * pipeline (Secs. 2-6) on this program's bitmatrix, built for inspection;
+ * CO/FU/SCHED exist for levels >= CO, FU for >= CO_FU, SCHED for
+ * CO_FU_SCHED. */
 ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, size_t cap, size_t *len);
 
 /* Device-to-device copy with a plain 16-byte-per-lane kernel: the HBM

@@ -41,13 +41,13 @@ class EcError(RuntimeError):
 
 class CompileOpts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("slot_budget", ctypes.c_uint32),
-                ("compress", ctypes.c_uint32), ("hoist", ctypes.c_uint32)]
+                ("compress", ctypes.c_uint32), ("block_strips", ctypes.c_uint32)]
 
 
 class ProgramInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
-        "peak_live", "n_loads", "n_stores", "n_words")] + [
+        "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
 
 
@@ -213,10 +213,10 @@ class Program:
 
 
 def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
-                   compress: int = COMPRESS_XORREPAIR, hoist: int = 0) -> Program:
+                   compress: int = COMPRESS_XORREPAIR, block_strips: int = 0) -> Program:
     er = list(erased)
     er_arr = (ctypes.c_int * max(1, len(er)))(*er)
-    opts = CompileOpts(level, slot_budget, compress, hoist)
+    opts = CompileOpts(level, slot_budget, compress, block_strips)
     h = ctypes.c_void_p()
     _check(lib().ec_compile_slp(n, p, _flat_gen(gen, n, p), er_arr, len(er), ctypes.byref(opts), ctypes.byref(h)),
            "ec_compile_slp")

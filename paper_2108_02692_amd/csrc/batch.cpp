@@ -51,9 +51,9 @@ namespace {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Waves per SIMD the executor reaches for a slot budget (VGPRs per lane:
-// 4 + 4K + the kernel's own registers, out of 512).
-int waves_per_simd(int slots) { return slots <= 16 ? 6 : slots <= 24 ? 4 : slots <= 32 ? 3 : 2; }
+// Waves per SIMD the executor reaches for a slot budget: VGPRs per lane are
+// 4 + 4K + a few of the kernel's own, allocated in granules of 8, out of 512.
+int waves_per_simd(int slots) { return slots <= 24 ? 4 : slots <= 38 ? 3 : 2; }
 
 }  // namespace
 

@@ -1,71 +1,62 @@
-// bytecode.hpp -- device bytecode of a compiled XOR program.
+// bytecode.hpp -- the executor's record format.
 //
-// One program runs once per tile (a 16-byte-per-lane, 1 KiB-per-wave slice
-// of every strip).  The executor holds K register slots of 16 bytes per lane
-// and one 16-byte accumulator (acc).  The compiler first produces a linear
-// stream of micro-ops, then packs it into fixed 16-word blocks; the device
-// only sees blocks.
+// A program is a sequence of variable-length records, each two header words
+// and n operand words (0 <= n <= 14), followed by 16 zero words (the executor
+// reads a fixed 16-word window at every record).  The machine has one
+// accumulator (16 B per lane) and K register slots; a record does, in this
+// order, what its kind asks:
 //
-// Micro-ops:
-//   PULL s        acc ^= slot[s]
-//   PUSH s        slot[s] ^= acc
-//   PUSHSET s     slot[s] = acc
-//   PUT s         slot[s] = acc
-//   STORE o       output strip o <- acc
-//   CLEAR         acc = 0
-//   LD s, c       slot[s] <- input strip c (asynchronous)
-//   WAIT n        wait until at most n vector memory ops are outstanding
-//   HALT          end of the tile
+//   kind      WAIT  PULL  LD   STORE  then the run
+//   RUN        -     -    -     -     (continuation: acc is kept)
+//   INPUT      x     x    -     -
+//   INPUT_LD   x     x    x     -
+//   VALUE      -     x    -     -
+//   STORE      -     x    -     x
+//   LOAD       -     -    x     -
+//   HALT       end of the program
 //
-// Device block: 16 words.  Word 0 (H0) and word 1 (H1) are headers; pull
-// operands occupy words 2 .. 2+np-1 and push operands words 16-nq .. 15
-// (np + nq <= 14).  A block executes, in this order:
-//   [LD] [WAIT] np x PULL [PUT] [STORE] nq x PUSH (or PUSHSET) [CLEAR] [HALT]
-//   H0: bits 3:0 np | bits 7:4 nq | bit 8 LD | bits 14:9 LD slot |
-//       bits 25:15 LD strip | bit 26 WAIT | bit 27 push runs set (PUSHSET)
-//   H1: bits 5:0 WAIT count | bit 6 PUT | bits 12:7 PUT slot | bit 13 STORE |
-//       bits 24:14 STORE strip | bit 25 CLEAR | bit 26 HALT
-//   operand word: 4 * slot (bits 7:0), the VGPR offset of the slot.
-// Input strip c is strip c % 8 of input argument c / 8; output strip o is
-// strip o % 8 of output argument o / 8.
+//   WAIT   s_waitcnt vmcnt(wait): the pulled slot's load has landed
+//   PULL   acc = slot[pull]
+//   LD     slot[ld] = 16 B per lane of strip (blk, j) of this tile
+//   STORE  strip (blk, j) of this tile = acc
+//   run    slot[op] ^= acc for every operand (an operand equal to the pulled
+//          slot clears it, which is how accumulators are returned to zero)
+//
+// Header word 0:  [7:0] 4*pull slot   [11:9] kind   [18:12] record bytes
+//                 (8 + 4n)   [27:19] byte offset of the run's entry in the
+//                 unrolled 14-step run table, (14 - n) * 20
+// Header word 1:  [8:0] 8*wait   [18:9] 16*ld slot   [23:19] blk   [26:24] j
+// Operand words:  4*slot.
+// Every other bit is zero.  The scaled fields are the byte offsets the
+// executor's computed jumps use directly.
 #pragma once
 
 #include <cstdint>
-#include <vector>
 
 namespace ec {
 namespace bc {
 
-// ---- linear micro-ops
-enum Kind : uint8_t { PULL, PUSH, PUSHSET, PUT, STORE, CLEAR, LD, WAIT, HALT };
-struct Micro {
-  Kind kind;
-  int16_t slot;   // PULL / PUSH / PUSHSET / PUT / LD
-  int16_t strip;  // LD input strip / STORE output strip
-  int16_t count;  // WAIT
-};
+enum Kind : uint32_t { RUN = 0, INPUT = 1, INPUT_LD = 2, VALUE = 3, STORE = 4, LOAD = 5, HALT = 6 };
 
-// ---- device blocks
-constexpr int kBlockWords = 16;
-constexpr int kMaxOperands = 14;  // np + nq
-constexpr int kMaxStrip = 2047;   // 11-bit strip fields
-constexpr int kMaxSlot = 63;      // 6-bit slot fields
-constexpr int kMaxVmcnt = 63;     // 6-bit vector memory counter
+constexpr int kMaxOps = 14;       // operands per record
+constexpr int kWindow = 16;       // words the executor reads per record
+constexpr int kRunStepBytes = 20; // s_set_gpr_idx_on + 4 x v_xor_b32 (VOP2)
+constexpr int kMaxWait = 63;      // vmcnt field
 
-constexpr uint32_t H0_LD = 1u << 8, H0_WAIT = 1u << 26, H0_SET = 1u << 27;
-constexpr uint32_t H1_PUT = 1u << 6, H1_STORE = 1u << 13, H1_CLEAR = 1u << 25, H1_HALT = 1u << 26;
-
-constexpr uint32_t h0_np(uint32_t h) { return h & 15u; }
-constexpr uint32_t h0_nq(uint32_t h) { return (h >> 4) & 15u; }
-constexpr uint32_t h0_ld_slot(uint32_t h) { return (h >> 9) & 63u; }
-constexpr uint32_t h0_ld_strip(uint32_t h) { return (h >> 15) & 0x7FFu; }
-constexpr uint32_t h1_wait(uint32_t h) { return h & 63u; }
-constexpr uint32_t h1_put_slot(uint32_t h) { return (h >> 7) & 63u; }
-constexpr uint32_t h1_store_strip(uint32_t h) { return (h >> 14) & 0x7FFu; }
-
-// Pack a linear micro-op stream into device blocks; the last block carries
-// HALT and one zero block follows, so the device may prefetch past HALT.
-std::vector<uint32_t> pack(const std::vector<Micro> &ops);
+constexpr uint32_t h0(uint32_t kind, uint32_t pull_slot, uint32_t n) {
+  return (4u * pull_slot) | (kind << 9) | ((8u + 4u * n) << 12) | (((uint32_t)kMaxOps - n) * kRunStepBytes << 19);
+}
+constexpr uint32_t h1(uint32_t wait, uint32_t ld_slot, uint32_t blk, uint32_t j) {
+  return (8u * wait) | ((16u * ld_slot) << 9) | (blk << 19) | (j << 24);
+}
+constexpr uint32_t h0_kind(uint32_t w) { return (w >> 9) & 7u; }
+constexpr uint32_t h0_pull(uint32_t w) { return (w & 0xffu) >> 2; }
+constexpr uint32_t h0_bytes(uint32_t w) { return (w >> 12) & 0x7fu; }
+constexpr uint32_t h0_runoff(uint32_t w) { return (w >> 19) & 0x1ffu; }
+constexpr uint32_t h1_wait(uint32_t w) { return (w & 0x1ffu) >> 3; }
+constexpr uint32_t h1_ld(uint32_t w) { return ((w >> 9) & 0x3ffu) >> 4; }
+constexpr uint32_t h1_blk(uint32_t w) { return (w >> 19) & 0x1fu; }
+constexpr uint32_t h1_j(uint32_t w) { return (w >> 24) & 7u; }
 
 }  // namespace bc
 }  // namespace ec

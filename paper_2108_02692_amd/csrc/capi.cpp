@@ -13,7 +13,7 @@
 #include "bytecode.hpp"
 #include "exec.hpp"
 #include "gf.hpp"
-#include "sched.hpp"
+#include "push.hpp"
 #include "slp.hpp"
 #include "program.hpp"
 
@@ -21,7 +21,17 @@ using namespace ec;
 
 namespace {
 
-bool supported_slots(uint32_t k) { return k == 16 || k == 24 || k == 32 || k == 40 || k == 48; }
+constexpr uint32_t kSlotBudgets[] = {24, 32, 36, 38, 40, 44, 48};  // executor kernels built
+
+// Record overhead of the executor in slot-XOR units: the unfolding trade-off
+// of a temporary (one record against the XORs it saves).
+constexpr int kRecordCost = 2;
+
+bool supported_slots(uint32_t k) {
+  for (uint32_t s : kSlotBudgets)
+    if (s == k) return true;
+  return false;
+}
 
 ec_status make_generator(int n, int p, uint8_t *gen, bool cauchy) {
   if (!gen || n < 1 || p < 0 || n + p > 64) return EC_ERR_ARG;
@@ -108,17 +118,9 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   }
   ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0};
   if (opts) o = *opts;
-  if (o.slot_budget == 0) {
-    // Default budget: the broadcast form needs the output rows plus a ring of
-    // at least 8 prefetch slots; pulled programs use the largest budget.
-    const int rows = 8 * (n_erased > 0 ? n_erased : p);
-    o.slot_budget = 48;
-    if (o.level == EC_LEVEL_PLAIN)
-      for (uint32_t k : {16u, 24u, 32u, 40u, 48u})
-        if ((int)k >= rows + 8) { o.slot_budget = k; break; }
-  }
-  if (o.level > EC_LEVEL_CO_FU_SCHED || !supported_slots(o.slot_budget) || o.compress > EC_COMPRESS_REPAIR)
-    return EC_ERR_UNSUPPORTED;
+  if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
+  if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
+  if (o.block_strips > (uint32_t)(8 * n)) return EC_ERR_ARG;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -126,7 +128,6 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   prog->p = p;
   prog->decode = n_erased > 0;
   prog->level = (int)o.level;
-  prog->slots = (int)o.slot_budget;
   const Mat g(gen, gen + (size_t)(n + p) * n);
   Mat rows;
   if (!prog->decode) {
@@ -138,70 +139,82 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     if (decode_rows(n, p, g, er, rows, prog->in_blocks) != 0) return EC_ERR_SINGULAR;
     prog->out_blocks = er;
   }
-  const int n_rows = (int)prog->out_blocks.size();
-  const std::vector<Bits> brows = bitmatrix_rows(n_rows, n, rows);
+  const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+  const std::vector<Bits> brows = bitmatrix_rows(n_out, n, rows);
   const int n_const = 8 * n;
-  prog->plain = plain_slp(brows, n_const);
-  prog->final_stage = &prog->plain;
-  if (o.level >= EC_LEVEL_CO) {
-    prog->co = xor_repair(brows, n_const, o.compress == EC_COMPRESS_XORREPAIR);
-    prog->final_stage = &prog->co;
-  }
-  if (o.level >= EC_LEVEL_CO_FU) {
-    prog->fu = fuse(prog->co);
-    prog->final_stage = &prog->fu;
-  }
-  if (o.level >= EC_LEVEL_CO_FU_SCHED) {
-    prog->sched = dfs_schedule(prog->fu);
-    prog->final_stage = &prog->sched;
-  }
-  // Every stage must still compute the bitmatrix rows (Sec. 4.1 semantics).
-  const std::vector<Bits> val = evaluate(*prog->final_stage);
-  for (size_t r = 0; r < brows.size(); ++r)
-    if (!(val[r] == brows[r])) return EC_ERR_UNSUPPORTED;
 
-  SchedOpts so;
-  so.slots = (int)o.slot_budget;
-  if (o.hoist) so.hoist = (int)o.hoist;
-  // The plain program runs in broadcast form (rows accumulate in slots, each
-  // input strip is loaded once) whenever the rows leave room for a ring of
-  // prefetch slots.  Compressed programs run as pulled statements: the
-  // level's own program if its live values fit the register slots, else
-  // with temporaries unfolded until they do, leaving slots for inputs.
-  prog->exec = *prog->final_stage;
-  int rc;
-  if (o.level == EC_LEVEL_PLAIN && n_rows * 8 + 2 <= so.slots) {
-    rc = schedule_broadcast(brows, n_const, so, prog->code);
+  // The paper's whole-matrix pipeline (Secs. 2-6), kept for inspection.
+  prog->plain = plain_slp(brows, n_const);
+  if (o.level >= EC_LEVEL_CO) prog->co = xor_repair(brows, n_const, o.compress == EC_COMPRESS_XORREPAIR);
+  if (o.level >= EC_LEVEL_CO_FU) prog->fu = fuse(prog->co);
+  if (o.level >= EC_LEVEL_CO_FU_SCHED) prog->sched = dfs_schedule(prog->fu);
+
+  // The executed program, in push form.
+  const int width = o.block_strips ? (int)o.block_strips : 8;
+  PushDag dag;
+  if (o.level == EC_LEVEL_PLAIN) {
+    dag = push_plain(brows, n_const);
   } else {
-    rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
-    for (int budget = so.slots - std::max(6, so.slots / 4); rc == -1 && budget >= 0; budget -= 2) {
-      prog->exec = fit_live_budget(*prog->final_stage, budget);
-      rc = schedule(prog->exec, n_const, 8 * n_rows, so, prog->code);
+    dag = push_blocked(brows, n_const, width, o.compress == EC_COMPRESS_XORREPAIR, o.level >= EC_LEVEL_CO_FU);
+    if (o.level >= EC_LEVEL_CO_FU_SCHED) {
+      push_unfold(dag, kRecordCost);
+      push_order(dag, width);
     }
   }
-  if (rc == -1) return EC_ERR_CAPACITY;
-  if (rc != 0) return EC_ERR_UNSUPPORTED;
-  {
-    const std::vector<Bits> ev = evaluate(prog->exec);
-    for (size_t r = 0; r < brows.size(); ++r)
-      if (!(ev[r] == brows[r])) return EC_ERR_UNSUPPORTED;
+  PushOpts po;
+  auto place = [&]() -> int {
+    if (o.slot_budget) {
+      po.slots = (int)o.slot_budget;
+      return push_schedule(dag, n_in, po, prog->code);
+    }
+    // smallest budget with one pass over the inputs and a ring of 6 loads
+    // beside the rows and the open temporaries
+    int rc = -1;
+    for (uint32_t k : kSlotBudgets) {
+      po.slots = (int)k;
+      rc = push_schedule(dag, n_in, po, prog->code);
+      if (rc == 0 && ((prog->code.passes == 1 && prog->code.ring >= 6) || k == 48)) break;
+    }
+    return rc;
+  };
+  int rc = place();
+  // Too many temporaries open for the budget: unfold more of them (in the
+  // limit every temporary is inlined and none is open) until it fits.
+  for (int cost : {4, 8, 16, 64, 1 << 20}) {
+    if (rc == 0 || o.level == EC_LEVEL_PLAIN) break;
+    push_unfold(dag, cost);
+    if (o.level >= EC_LEVEL_CO_FU_SCHED) push_order(dag, width);
+    rc = place();
   }
+  if (rc != 0) return EC_ERR_CAPACITY;
+  {
+    const std::vector<Bits> val = push_eval(dag);
+    for (size_t r = 0; r < brows.size(); ++r)
+      if (!(val[r] == brows[r])) return EC_ERR_UNSUPPORTED;
+  }
+  prog->exec = push_as_slp(dag);
+  prog->slots = po.slots;
+  if (!simulate_code(prog->code.words, prog->slots, n_in, n_out, brows)) return EC_ERR_UNSUPPORTED;
 
   ec_program_info &info = prog->info;
   info.n = (uint32_t)n;
   info.p = (uint32_t)p;
   info.n_in = (uint32_t)prog->in_blocks.size();
-  info.n_out = (uint32_t)n_rows;
+  info.n_out = (uint32_t)n_out;
   const Slp &f = prog->exec;
   info.n_stmt = (uint32_t)f.stmts.size();
   info.n_xor2 = (uint32_t)count_xor(f);
   info.n_mem = (uint32_t)count_mem(f);
-  info.nvar = (uint32_t)dfs_pebbles(f);
+  info.nvar = (uint32_t)f.stmts.size();
   info.plain_xor2 = (uint32_t)count_xor(prog->plain);
-  info.slots = (uint32_t)prog->code.slots_used;
-  info.peak_live = (uint32_t)prog->code.peak_live;
+  info.slots = (uint32_t)prog->slots;
+  info.peak_open = (uint32_t)prog->code.peak_open;
+  info.ring = (uint32_t)prog->code.ring;
+  info.passes = (uint32_t)prog->code.passes;
   info.n_loads = (uint32_t)prog->code.n_loads;
   info.n_stores = (uint32_t)prog->code.n_stores;
+  info.n_records = (uint32_t)prog->code.n_records;
+  info.n_ops = (uint32_t)prog->code.n_ops;
   info.n_words = (uint32_t)prog->code.words.size();
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();

@@ -1,0 +1,320 @@
+#!/usr/bin/env python3
+"""Writes exec.hip, the gfx950 executor, from the tables below.
+
+Run from this directory after changing it:  python3 gen_exec.py
+The record format it interprets is described in bytecode.hpp.
+"""
+import os
+
+SLOT_BUDGETS = (24, 32, 36, 38, 40, 44, 48)
+WA, WB = 36, 52          # the two 16-SGPR record windows
+MAX_OPS = 14
+STEP_BYTES = 20
+MAX_WAIT = 63
+
+
+def groups(K):
+    """Pinned VGPR groups covering the K slots (v[4 : 4+4K)): 32-register
+    groups, then a 16 and an 8 if needed."""
+    out, lo, left = [], 4, 4 * K
+    for size in (32, 16, 8):
+        while left >= size:
+            out.append((lo, size))
+            lo += size
+            left -= size
+    assert left == 0, K
+    return out
+
+
+def vtype(size):
+    return {32: "v32u", 16: "v16u", 8: "v8u"}[size]
+
+
+def operands(K, mode):
+    """Asm operand list for the accumulator and the slot groups."""
+    c = {"inout": "+", "out": "="}[mode]
+    ops = ['"%s{v[0:3]}"(acc)' % c]
+    for i, (lo, size) in enumerate(groups(K)):
+        ops.append('"%s{v[%d:%d]}"(g%d)' % (c, lo, lo + size - 1, i))
+    return ", ".join(ops)
+
+
+def decls(K):
+    return "v4u acc;\n  " + " ".join("%s g%d;" % (vtype(size), i) for i, (lo, size) in enumerate(groups(K)))
+
+
+def asm_lines(lines):
+    return "\n".join('      "%s\\n\\t"' % l for l in lines)
+
+
+CLOBBERS = ", ".join('"s%d"' % r for r in range(36, 96)) + ', "scc"'
+
+
+def handler(K, kind, W, O, run_base, h_other):
+    """One record handler for window W (the next record is loaded into O)."""
+    nxt = ["s_bfe_u32 s74, s%d, 0x7000c" % W,           # record bytes
+           "s_add_u32 s68, s68, s74",
+           "s_load_dwordx16 s[%d:%d], %%[prog], s68" % (O, O + 15)]
+    wait = ["s_and_b32 s74, s%d, 0x1f8" % (W + 1),     # 8 * wait
+            "s_add_u32 s80, s94, s74",
+            "s_addc_u32 s81, s95, 0",
+            "s_swappc_b64 s[78:79], s[80:81]"]
+    pull = ["s_and_b32 s74, s%d, 0xff" % W,            # 4 * pull slot
+            "s_set_gpr_idx_on s74, gpr_idx(SRC0)",
+            "v_mov_b32_e32 v0, v4", "v_mov_b32_e32 v1, v5",
+            "v_mov_b32_e32 v2, v6", "v_mov_b32_e32 v3, v7",
+            "s_set_gpr_idx_off"]
+    addr = ["s_bfe_u32 s74, s%d, 0x50013" % (W + 1),   # block
+            "v_readlane_b32 s72, %[tlo], s74",
+            "v_readlane_b32 s73, %[thi], s74",
+            "s_bfe_u32 s75, s%d, 0x30018" % (W + 1),   # strip of the block
+            "s_mul_i32 s75, s75, %[sl]",
+            "s_add_u32 s72, s72, s75",
+            "s_addc_u32 s73, s73, 0",
+            # five wait states between the v_readlane SGPR writes and the
+            # memory instruction reading the address
+            "s_nop 4"]
+    ld = ["s_bfe_u32 s74, s%d, 0xa0009" % (W + 1),     # 16 * ld slot
+          # (the host validates every field; the clamps keep a computed jump
+          # inside its table whatever the word holds)
+          "s_min_u32 s74, s74, %d" % (16 * (K - 1)),
+          "s_add_u32 s80, s92, s74",
+          "s_addc_u32 s81, s93, 0",
+          "s_swappc_b64 s[78:79], s[80:81]"]
+    store = ["global_store_dwordx4 %[voff], v[0:3], s[72:73]",
+             # one wait state before a VALU may overwrite the store's data
+             "s_nop 1"]
+    run = ["s_bfe_u32 s74, s%d, 0x90013" % W,          # run entry offset
+           "s_min_u32 s74, s74, %d" % (MAX_OPS * STEP_BYTES),
+           "s_add_u32 s80, s%d, s74" % run_base,
+           "s_addc_u32 s81, s%d, 0" % (run_base + 1),
+           "s_setpc_b64 s[80:81]"]
+    body = {
+        0: nxt + run,
+        1: nxt + wait + pull + run,
+        2: nxt + wait + pull + addr + ld + run,
+        3: nxt + pull + run,
+        4: nxt + pull + addr + store + run,
+        5: nxt + addr + ld + run,
+        6: ["s_branch 99f"],
+        7: ["s_branch 99f"],
+    }[kind]
+    return [".p2align 9"] + body
+
+
+def run_table(W, O, h_other):
+    lines = []
+    for i in range(MAX_OPS):
+        lines += ["s_set_gpr_idx_on s%d, gpr_idx(SRC0,DST)" % (W + 15 - i),
+                  "v_xor_b32_e32 v4, v4, v0", "v_xor_b32_e32 v5, v5, v1",
+                  "v_xor_b32_e32 v6, v6, v2", "v_xor_b32_e32 v7, v7, v3"]
+    lines += ["s_set_gpr_idx_off",
+              "s_waitcnt lgkmcnt(0)",                 # the next record's window
+              "s_and_b32 s74, s%d, 0xe00" % O,        # its kind * 512
+              "s_add_u32 s80, s%d, s74" % h_other,
+              "s_addc_u32 s81, s%d, 0" % (h_other + 1),
+              "s_setpc_b64 s[80:81]"]
+    return lines
+
+
+def program_asm(K):
+    L = ["s_mov_b32 s68, 0",
+         "s_load_dwordx16 s[%d:%d], %%[prog], 0x0" % (WA, WA + 15),
+         "s_getpc_b64 s[82:83]",
+         "90:"]
+    for reg, label in ((84, 91), (86, 92), (88, 93), (90, 94), (92, 95), (94, 96)):
+        L += ["s_add_u32 s%d, s82, %df-90b" % (reg, label), "s_addc_u32 s%d, s83, 0" % (reg + 1)]
+    L += ["s_waitcnt lgkmcnt(0)",
+          "s_and_b32 s74, s%d, 0xe00" % WA,
+          "s_add_u32 s80, s84, s74",
+          "s_addc_u32 s81, s85, 0",
+          "s_setpc_b64 s[80:81]"]
+    for W, O, run_base, h_other, label in ((WA, WB, 88, 86, 91), (WB, WA, 90, 84, 92)):
+        for kind in range(8):
+            h = handler(K, kind, W, O, run_base, h_other)
+            if kind == 0:
+                h = h[:1] + ["%d:" % label] + h[1:]
+            L += h
+    L += [".p2align 2", "93:"] + run_table(WA, WB, 86)
+    L += ["94:"] + run_table(WB, WA, 84)
+    L += ["95:"]
+    for k in range(K):
+        L += ["global_load_dwordx4 v[%d:%d], %%[voff], s[72:73]" % (4 + 4 * k, 7 + 4 * k),
+              "s_setpc_b64 s[78:79]", "s_nop 0"]
+    L += ["96:"]
+    for k in range(MAX_WAIT + 1):
+        L += ["s_waitcnt vmcnt(%d)" % k, "s_setpc_b64 s[78:79]"]
+    L += ["99:"]
+    return L
+
+
+HEAD = r'''// exec.hip -- gfx950 executor for push-form XOR programs.
+// GENERATED by gen_exec.py -- edit that file and regenerate.
+//
+// One wave runs the whole program on one tile: 64 lanes x 16 bytes = 1 KiB
+// of every input and output strip (the blocked loop of Sec. 6.1; the tile is
+// the paper's block size).  The accumulator is pinned to v[0:3] and K
+// register slots of 16 bytes per lane to v[4 : 4+4K).  The program is a
+// stream of records (bytecode.hpp) read through the scalar cache, two
+// 16-word windows in turn, the next record's window loading while the
+// current record runs.  The interpreter is one asm block:
+//  * dispatch: the record's kind * 512 is the byte offset of its handler
+//    (handlers are 512-byte aligned), so a record costs one computed jump;
+//  * pull: acc = slot[i] through s_set_gpr_idx_on (VGPR indexing);
+//  * run: a computed jump into 14 unrolled 20-byte steps, each an indexed
+//    slot ^= acc (four v_xor_b32), entered so that exactly the record's
+//    operands execute; the run falls through into the next dispatch;
+//  * strip loads land in their slot through a table of K global_load_dwordx4
+//    (16 B per lane, 1 KiB per wave, coalesced), stores write acc; vmcnt
+//    waits are the host's exact counts, through a 64-entry table.
+// Temporaries never leave the registers (the deforestation of Sec. 5); the
+// host validates every record before the program reaches the device.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "bytecode.hpp"
+#include "exec.hpp"
+
+namespace ec {
+
+typedef uint32_t v32u __attribute__((ext_vector_type(32)));
+typedef uint32_t v16u __attribute__((ext_vector_type(16)));
+typedef uint32_t v8u __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+static_assert(bc::kMaxOps == %(MAX_OPS)d && bc::kRunStepBytes == %(STEP)d && bc::kMaxWait == %(MAXW)d,
+              "record format and executor tables disagree");
+
+typedef const __attribute__((address_space(4))) StripeDesc *ConstDescPtr;
+typedef const __attribute__((address_space(4))) uint32_t *ConstU32Ptr;
+
+'''
+
+PER_K = r'''// ---- %(K)d slots
+#define EC_INIT_%(K)d asm volatile(%(INIT)s : %(OUT)s)
+#define EC_RUN_%(K)d(prog, voff, tlo, thi, sl)  \
+  asm volatile(                                  \
+%(PROGRAM)s
+      : %(INOUT)s                                \
+      : [prog] "s"(prog), [voff] "v"(voff), [tlo] "v"(tlo), [thi] "v"(thi), [sl] "s"(sl) \
+      : %(CLOB)s)
+
+__global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  // wave index as a scalar: every per-tile address below is wave-uniform
+  const uint32_t wave = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t n_waves = gridDim.x * 4u;
+  // lane b holds the pointer of block b
+  uint64_t tab = lane < (uint32_t)kMaxBlocks ? a.blk[lane] : 0ull;
+  // wait for the table here, once: the compiler cannot see the executor's
+  // own memory operations and would otherwise wait for them at every tile
+  asm volatile("s_waitcnt vmcnt(0)" : "+v"(tab));
+  const uint32_t voff = lane * 16u;
+  const uint32_t sl = (uint32_t)a.strip_len;
+  const uint32_t *prog = a.prog;
+  %(DECLS)s
+  EC_INIT_%(K)d;
+  for (uint32_t tile = wave; tile < a.n_tiles; tile += n_waves) {
+    const uint64_t toff = (uint64_t)tile * kTileBytes;
+    const uint64_t t = tab + toff;
+    const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+    if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
+  }
+}
+
+// Waves take (stripe, first tile) work items from a device counter; an item
+// covers tiles_per_item tiles of its stripe.  Descriptors and items are
+// read-only for the launch and read through the scalar cache.
+__global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t voff = lane * 16u;
+  %(DECLS)s
+  EC_INIT_%(K)d;
+  for (;;) {
+    uint32_t it = 0;
+    if (lane == 0) it = atomicAdd(a.counter, 1u);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= a.n_items) break;
+    const uint32_t stripe = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it];
+    const uint32_t tile = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it + 1];
+    ConstDescPtr d = (ConstDescPtr)(uintptr_t)(a.stripes + stripe);
+    const uint32_t *prog = d->prog;
+    const uint32_t sl = d->strip_len;
+    const uint64_t tab = lane < (uint32_t)kMaxBlocks ? a.stripes[stripe].blk[lane] : 0ull;
+    for (uint32_t k = 0; k < a.tiles_per_item; ++k) {
+      const uint64_t toff = (uint64_t)(tile + k) * kTileBytes;
+      if (toff >= sl) break;
+      const uint64_t t = tab + toff;
+      const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+      if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
+    }
+  }
+}
+
+'''
+
+TAIL = r'''__global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
+
+int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t stream) {
+  switch (slots) {
+%(EXEC_CASES)s
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.counter);
+  switch (slots) {
+%(BATCH_CASES)s
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Plain device copy (16 B per lane, grid-stride): the bandwidth ceiling the
+// executor is compared with, and the calibration kernel for byte counters.
+__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                   uint64_t n16) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+int copy_launch(const void *src, void *dst, size_t bytes, hipStream_t stream) {
+  const uint64_t n16 = bytes / 16;
+  const int grid = (int)std::min<uint64_t>((n16 + 255) / 256, 256 * 32);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, (const uint4 *)src, (uint4 *)dst, n16);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ec
+'''
+
+
+def init_asm(K):
+    regs = ["v_mov_b32_e32 v%d, 0" % r for r in range(4 + 4 * K)]
+    return '"' + "\\n\\t".join(regs) + '"'
+
+
+def main():
+    out = HEAD % {"MAX_OPS": MAX_OPS, "STEP": STEP_BYTES, "MAXW": MAX_WAIT}
+    for K in SLOT_BUDGETS:
+        prog = "\n".join('      "%s\\n\\t"                     \\' % l for l in program_asm(K))
+        out += PER_K % {"K": K, "INIT": init_asm(K), "OUT": operands(K, "out"), "INOUT": operands(K, "inout"),
+                        "PROGRAM": prog, "CLOB": CLOBBERS, "DECLS": decls(K)}
+    exec_cases = "\n".join(
+        "    case %d: hipLaunchKernelGGL(slp_exec_kernel_%d, dim3(grid), dim3(256), 0, stream, a); break;" % (K, K)
+        for K in SLOT_BUDGETS)
+    batch_cases = "\n".join(
+        "    case %d: hipLaunchKernelGGL(slp_batch_kernel_%d, dim3(grid), dim3(256), 0, stream, a); break;" % (K, K)
+        for K in SLOT_BUDGETS)
+    out += TAIL % {"EXEC_CASES": exec_cases, "BATCH_CASES": batch_cases}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "exec.hip")
+    with open(path, "w") as f:
+        f.write(out)
+
+
+if __name__ == "__main__":
+    main()

@@ -8,7 +8,7 @@
 #include <vector>
 
 #include "../../include/ec.h"
-#include "sched.hpp"
+#include "push.hpp"
 #include "slp.hpp"
 
 struct ec_program {
@@ -19,10 +19,9 @@ struct ec_program {
   int level = EC_LEVEL_CO_FU_SCHED;
   int slots = 32;
   std::vector<int> in_blocks, out_blocks;
-  ec::Slp plain, co, fu, sched;  // pipeline stages (co/fu/sched empty for PLAIN)
-  const ec::Slp *final_stage = nullptr;
-  ec::Slp exec;                  // the program the executor runs (fitted to the slot budget)
-  ec::SchedResult code;
+  ec::Slp plain, co, fu, sched;  // the paper's whole-matrix stages (co/fu/sched per level)
+  ec::Slp exec;                  // the push-form program the executor runs, as an SLP
+  ec::PushCode code;
   ec_program_info info{};
   std::mutex mu;
   std::map<int, uint32_t *> dev_words;  // device -> bytecode copy

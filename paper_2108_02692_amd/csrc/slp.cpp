@@ -240,76 +240,6 @@ Slp dfs_schedule(const Slp &in) {
   return out;
 }
 
-// ---------------------------------------------------------------- budget fitting
-namespace {
-
-// Live temporaries after each statement; returns the peak and the set live
-// at the (first) peak.
-int live_peak(const Slp &p, std::vector<int> *at_peak) {
-  std::unordered_map<int, int> last;
-  for (size_t i = 0; i < p.stmts.size(); ++i)
-    for (int o : p.stmts[i].ops)
-      if (!is_const(o) && o != kZero) last[o] = (int)i;
-  std::set<int> live;
-  int peak = 0;
-  for (size_t i = 0; i < p.stmts.size(); ++i) {
-    for (int o : p.stmts[i].ops) {
-      auto it = last.find(o);
-      if (it != last.end() && it->second == (int)i) live.erase(o);
-    }
-    if (last.count(p.stmts[i].var)) live.insert(p.stmts[i].var);
-    if ((int)live.size() > peak) {
-      peak = (int)live.size();
-      if (at_peak) at_peak->assign(live.begin(), live.end());
-    }
-  }
-  return peak;
-}
-
-}  // namespace
-
-int peak_live_temps(const Slp &p) { return live_peak(p, nullptr); }
-
-Slp fit_live_budget(const Slp &in, int budget) {
-  Slp p = dfs_schedule(in);
-  const std::set<int> outset(in.outputs.begin(), in.outputs.end());
-  for (;;) {
-    std::vector<int> live;
-    if (live_peak(p, &live) <= budget) return p;
-    std::unordered_map<int, int> uses, arity;
-    for (const Stmt &s : p.stmts) {
-      arity[s.var] = (int)s.ops.size();
-      for (int o : s.ops)
-        if (!is_const(o) && o != kZero) ++uses[o];
-    }
-    int best = -1;
-    long best_cost = 0;
-    for (int t : live) {
-      if (outset.count(t)) continue;
-      const long cost = (long)(uses[t] - 1) * (arity[t] - 1);
-      if (best < 0 || cost < best_cost || (cost == best_cost && t < best)) { best = t; best_cost = cost; }
-    }
-    if (best < 0) return p;  // only outputs live: nothing left to unfold
-    std::vector<int> tops;
-    for (const Stmt &s : p.stmts)
-      if (s.var == best) tops = s.ops;
-    std::vector<Stmt> kept;
-    for (Stmt s : p.stmts) {
-      if (s.var == best) continue;
-      auto it = std::find(s.ops.begin(), s.ops.end(), best);
-      if (it != s.ops.end()) {
-        std::vector<int> spliced(s.ops.begin(), it);
-        spliced.insert(spliced.end(), tops.begin(), tops.end());
-        spliced.insert(spliced.end(), it + 1, s.ops.end());
-        s.ops = cancel_ops(spliced);
-      }
-      kept.push_back(s);
-    }
-    p.stmts.swap(kept);
-    p = dfs_schedule(p);
-  }
-}
-
 // ---------------------------------------------------------------- measures
 std::vector<Bits> evaluate(const Slp &p) {
   std::unordered_map<int, Bits> env;

@@ -65,16 +65,6 @@ Slp fuse(const Slp &in);
 // DFS post-order over the computation graph (Sec. 6.6).
 Slp dfs_schedule(const Slp &in);
 
-// Register-budget fitting (the GPU counterpart of the paper's cache bound):
-// while more than `budget` temporaries are live at once in the DFS order,
-// unfold the live temporary whose unfolding adds the fewest XORs
-// ((uses - 1) * (arity - 1); ties to the lowest variable) into its users,
-// then re-schedule.  Returns the DFS-ordered result.
-Slp fit_live_budget(const Slp &in, int budget);
-
-// Peak number of simultaneously live temporaries in statement order.
-int peak_live_temps(const Slp &p);
-
 // Set-semantics value of every returned term.
 std::vector<Bits> evaluate(const Slp &p);
 

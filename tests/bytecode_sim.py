@@ -1,112 +1,104 @@
-"""Symbolic simulator of the executor's device bytecode (test helper).
+"""Independent simulator of the executor's record stream (written from the
+format described in csrc/bytecode.hpp, sharing no code with the library).
 
-Written from the block format documented in ``csrc/bytecode.hpp``, not from
-the emitter: it walks the 16-word blocks as the device does, tracks every
-slot's value as a set of input strips (the set semantics of Sec. 4.1), and
-models the in-order vector-memory counter, so it reports a read of a slot
-whose load may still be in flight, a register write racing a load, an
-uninitialised read, or a wrong output.  Returns {output strip: bitset}.
+Slots hold values under the set semantics of Sec. 4.1 (a Python int whose bit
+c stands for input strip c).  The vector memory counter is modelled exactly:
+a load lands only when a WAIT retires it (in issue order, stores included),
+so reading or accumulating into a slot whose load may still be in flight is
+an error, as is loading into such a slot.  The program is run for several
+consecutive tiles from all-zero slots, each tile starting from the state the
+previous one left, and every tile must store the same values.
 """
 
-BLOCK = 16
+KINDS = {0: "RUN", 1: "INPUT", 2: "INPUT_LD", 3: "VALUE", 4: "STORE", 5: "LOAD", 6: "HALT"}
 
 
 class SimError(AssertionError):
     pass
 
 
-def simulate(words, slots, n_in_strips, n_out_strips, max_vmcnt=63):
-    if len(words) % BLOCK:
-        raise SimError("program is not a whole number of blocks")
-    val = {}          # slot -> bitset value
-    pending = {}      # slot -> vm sequence of the load filling it
-    issued = 0
-    done_upto = -1
-    acc = 0
-    out = {}
-    pc = 0
+def fields(h0, h1):
+    return {
+        "pull4": h0 & 0xFF, "b8": (h0 >> 8) & 1, "kind": (h0 >> 9) & 7, "bytes": (h0 >> 12) & 0x7F,
+        "runoff": (h0 >> 19) & 0x1FF, "h0_hi": h0 >> 28,
+        "wait8": h1 & 0x1FF, "ld16": (h1 >> 9) & 0x3FF, "blk": (h1 >> 19) & 0x1F, "j": (h1 >> 24) & 7,
+        "h1_hi": h1 >> 27,
+    }
 
-    def ready(s):
-        return pending.get(s, -1) <= done_upto
 
-    def check_slot(s, what):
-        if s >= slots:
-            raise SimError("%s slot %d out of range" % (what, s))
+def check(cond, msg):
+    if not cond:
+        raise SimError(msg)
 
-    def read(s):
-        if s not in val:
-            raise SimError("read of never-written slot %d" % s)
-        if not ready(s):
-            raise SimError("read of slot %d before its load completed" % s)
-        return val[s]
 
-    def write(s):
-        if not ready(s):
-            raise SimError("write to slot %d while a load into it is in flight" % s)
-        pending.pop(s, None)
-
-    while True:
-        if pc + 2 * BLOCK > len(words):
-            raise SimError("block at %d has no read-ahead block after it" % pc)
-        h0, h1 = words[pc], words[pc + 1]
-        np_, nq = h0 & 15, (h0 >> 4) & 15
-        if np_ + nq > 14:
-            raise SimError("too many operands")
-        ops = words[pc + 2: pc + BLOCK]
-        for k, o in enumerate(ops):
-            used = k < np_ or k >= 14 - nq
-            if (o & 3 or o >> 8) and used:
-                raise SimError("bad operand word")
-            if not used and o:
-                raise SimError("unused operand word is not zero")
-        if h0 & (1 << 8):  # LD
-            s, c = (h0 >> 9) & 63, (h0 >> 15) & 0x7FF
-            check_slot(s, "LD")
-            if c >= n_in_strips:
-                raise SimError("LD strip out of range")
-            if not ready(s):
-                raise SimError("LD into slot %d while its previous load is in flight" % s)
-            val[s] = 1 << c
-            pending[s] = issued
-            issued += 1
-            if issued - 1 - done_upto > max_vmcnt + 1:
-                raise SimError("more vector memory ops outstanding than the counter holds")
-        if h0 & (1 << 26):  # WAIT
-            done_upto = max(done_upto, issued - 1 - (h1 & 63))
-        for k in range(np_):  # PULL
-            s = ops[k] >> 2
-            check_slot(s, "PULL")
-            acc ^= read(s)
-        if h1 & (1 << 6):  # PUT
-            s = (h1 >> 7) & 63
-            check_slot(s, "PUT")
-            write(s)
-            val[s] = acc
-        if h1 & (1 << 13):  # STORE
-            o = (h1 >> 14) & 0x7FF
-            if o >= n_out_strips:
-                raise SimError("STORE out of range")
-            out[o] = acc
-            issued += 1
-        for k in range(14 - nq, 14):  # PUSH / PUSHSET
-            s = ops[k] >> 2
-            check_slot(s, "PUSH")
-            if h0 & (1 << 27):
-                write(s)
-                val[s] = acc
-            else:
-                cur = read(s)
-                write(s)
-                val[s] = cur ^ acc
-        if h1 & (1 << 25):
-            acc = 0
-        if h0 >> 28 or h1 >> 27:
-            raise SimError("reserved header bits set")
-        pc += BLOCK
-        if h1 & (1 << 26):  # HALT
-            break
-    if acc != 0:
-        raise SimError("accumulator not cleared at HALT")
-    if pc + BLOCK != len(words):
-        raise SimError("words after the read-ahead block")
-    return out
+def simulate(words, slots, n_in_blocks, n_out_blocks, tiles=2):
+    """Returns {output strip index: value} (identical for every tile)."""
+    val = [0] * slots
+    busy = [False] * slots
+    first = None
+    for _ in range(tiles):
+        vm = []
+        out = {}
+        acc = 0
+        pc = 0
+        while True:
+            check(pc + 16 <= len(words), "window past the end at %d" % pc)
+            f = fields(words[pc], words[pc + 1])
+            kind = KINDS.get(f["kind"])
+            check(kind is not None, "bad kind at %d" % pc)
+            if kind == "HALT":
+                check(words[pc] >> 12 & 0x7F == 8 and words[pc + 1] == 0, "HALT fields")
+                check(all(w == 0 for w in words[pc + 2:]), "words after HALT")
+                check(len(words) - pc >= 18, "no zero window after HALT")
+                break
+            check(f["b8"] == 0 and f["h0_hi"] == 0 and f["h1_hi"] == 0, "reserved bits at %d" % pc)
+            nb = f["bytes"]
+            check(nb >= 8 and nb % 4 == 0 and nb <= 64, "record size at %d" % pc)
+            n = (nb - 8) // 4
+            check(f["runoff"] == (14 - n) * 20, "run entry at %d" % pc)
+            check(f["pull4"] % 4 == 0, "pull field")
+            pull = f["pull4"] // 4
+            pulls = kind in ("INPUT", "INPUT_LD", "VALUE", "STORE")
+            loads = kind in ("INPUT_LD", "LOAD")
+            waits = kind in ("INPUT", "INPUT_LD")
+            check(pulls or pull == 0, "stray pull field at %d" % pc)
+            check(waits or f["wait8"] == 0, "stray wait at %d" % pc)
+            check(f["wait8"] % 8 == 0 and f["ld16"] % 16 == 0, "scaled fields at %d" % pc)
+            check(loads or f["ld16"] == 0, "stray load slot at %d" % pc)
+            check(loads or kind == "STORE" or (f["blk"] == 0 and f["j"] == 0), "stray strip at %d" % pc)
+            if waits:
+                keep = f["wait8"] // 8
+                while len(vm) > keep:
+                    s = vm.pop(0)
+                    if s is not None:
+                        busy[s] = False
+            if pulls:
+                check(pull < slots, "pull slot range")
+                check(not busy[pull], "pull of slot %d before its load landed (pc %d)" % (pull, pc))
+                acc = val[pull]
+            if loads:
+                s = f["ld16"] // 16
+                check(s < slots and f["blk"] < n_in_blocks, "load fields at %d" % pc)
+                check(not busy[s], "load into slot %d with a load in flight" % s)
+                val[s] = 1 << (8 * f["blk"] + f["j"])
+                busy[s] = True
+                vm.append(s)
+            if kind == "STORE":
+                check(n_in_blocks <= f["blk"] < n_in_blocks + n_out_blocks, "store block at %d" % pc)
+                o = 8 * (f["blk"] - n_in_blocks) + f["j"]
+                check(o not in out, "strip %d stored twice" % o)
+                out[o] = acc
+                vm.append(None)
+            for q in range(n):
+                w = words[pc + 2 + q]
+                check(w % 4 == 0 and w // 4 < slots, "operand at %d" % pc)
+                s = w // 4
+                check(not busy[s], "XOR into slot %d with a load in flight" % s)
+                val[s] ^= acc
+            pc += 2 + n
+        check(not any(busy), "load left unconsumed")
+        if first is None:
+            first = out
+        else:
+            check(out == first, "a later tile stored different values")
+    return first

@@ -37,33 +37,84 @@ def test_status_strings():
         assert E.ec_status_str(s) and E.ec_status_str(s) != "unknown status"
 
 
+SLOT_BUDGETS = [24, 32, 36, 38, 40, 44, 48]
+OBJDUMP = os.path.join(os.path.dirname(_build.HIPCC), "..", "llvm", "bin", "llvm-objdump")
+
+
 @pytest.fixture(scope="module")
-def kernel_asm(tmp_path_factory):
-    out = tmp_path_factory.mktemp("isa") / "exec.s"
-    cmd = [_build.HIPCC, "-x", "hip"] + _build.DEVICE_FLAGS + ["-O3", "-std=c++17", "--cuda-device-only", "-S",
-                                                               os.path.join(_build.CSRC, "exec.hip"), "-o", str(out)]
-    subprocess.run(cmd, check=True, capture_output=True)
-    return out.read_text()
+def built(tmp_path_factory):
+    """Assembly and disassembly of this build's executor (gfx950)."""
+    d = tmp_path_factory.mktemp("isa")
+    base = [_build.HIPCC, "-x", "hip"] + _build.DEVICE_FLAGS + ["-O3", "-std=c++17", "--cuda-device-only",
+                                                                "-I", os.path.join(ROOT, "include")]
+    src = os.path.join(_build.CSRC, "exec.hip")
+    subprocess.run(base + ["-S", src, "-o", str(d / "exec.s")], check=True, capture_output=True)
+    subprocess.run(base + ["--no-gpu-bundle-output", "-c", src, "-o", str(d / "exec.co")], check=True,
+                   capture_output=True)
+    dis = subprocess.run([OBJDUMP, "-d", "--no-show-raw-insn", str(d / "exec.co")], check=True,
+                         capture_output=True, text=True).stdout
+    return (d / "exec.s").read_text(), dis
 
 
-def kernels(asm):
-    return re.findall(r"^(_ZN2ec15slp_exec_kernelILi(\d+)EEEvNS_8ExecArgsE):[^\n]*\n(.*?)s_endpgm", asm, flags=re.S | re.M)
+def kernel_names():
+    for K in SLOT_BUDGETS:
+        yield K, "_ZN2ec%d%s_kernel_%dENS_%d%sE" % (18, "slp_exec", K, 8, "ExecArgs")
+        yield K, "_ZN2ec%d%s_kernel_%dENS_%d%sE" % (19, "slp_batch", K, 9, "BatchArgs")
 
 
-def test_executor_isa(kernel_asm):
-    ks = kernels(kernel_asm)
-    assert sorted(int(k) for _, k, _ in ks) == [16, 24, 32, 40, 48]
-    for name, K, body in ks:
-        # no scratch (spills) in the executor
-        assert "scratch_" not in body, name
+def instructions(dis, name):
+    m = re.search(r"<%s>:\n(.*?)s_endpgm" % re.escape(name), dis, re.S)
+    assert m, name
+    out = {}
+    for line in m.group(1).splitlines():
+        mm = re.match(r"\s+(\S.*?)\s+//\s+([0-9A-F]+):", line)
+        if mm:
+            out[int(mm.group(2), 16)] = mm.group(1).strip()
+    return out
+
+
+def test_executor_isa(built):
+    asm, _ = built
+    meta = dict(re.findall(r"\.name:\s+(\S+)\n(?:.*\n)*?\s+\.vgpr_count:\s+(\d+)", asm))
+    scratch = dict(re.findall(r"\.name:\s+(\S+)\n(?:.*\n)*?\s+\.private_segment_fixed_size:\s+(\d+)", asm))
+    for K, name in kernel_names():
+        body = re.search(r"^%s:[^\n]*\n(.*?)s_endpgm" % re.escape(name), asm, re.S | re.M).group(1)
+        assert scratch[name] == "0", name  # no spills
         # m0 carries the VGPR index; only the executor's own asm may touch it
         outside = re.sub(r";;#ASMSTART.*?;;#ASMEND", "", body, flags=re.S)
         assert not re.search(r"\bm0\b", outside), name
-        # every strip load/store uses a scalar base address
-        for m in re.finditer(r"global_(load|store)_dwordx4 .*", body):
-            assert re.search(r", s\[\d+:\d+\]", m.group(0)), m.group(0)
-    meta = dict(re.findall(r"\.name:\s+(_ZN2ec15slp_exec_kernelILi\d+EEEvNS_8ExecArgsE)\n(?:.*\n)*?\s+\.vgpr_count:\s+(\d+)",
-                           kernel_asm))
-    for name, K, _ in ks:
-        if name in meta:
-            assert int(meta[name]) <= 4 + 4 * int(K) + 16, (name, meta[name])
+        vgprs = int(meta[name])
+        assert vgprs <= 4 + 4 * K + 12, (name, vgprs)
+        # the occupancy the batch launcher assumes (granules of 8 of 512)
+        waves = 512 // (-(-vgprs // 8) * 8)
+        assert waves >= (4 if K <= 24 else 3 if K <= 38 else 2), (name, vgprs)
+
+
+def test_interpreter_layout(built):
+    """The host encodes byte offsets into the executor's tables; check them
+    against this build: handlers 512 bytes apart, 20-byte run steps reading
+    window words 15..2, 16-byte load entries, 8-byte wait entries."""
+    _, dis = built
+    for K, name in kernel_names():
+        ins = instructions(dis, name)
+        addrs = sorted(ins)
+        gp = [a for a in addrs if ins[a] == "s_getpc_b64 s[82:83]"]
+        assert len(gp) == 1, name
+        i = addrs.index(gp[0])
+        base = {}
+        for a in addrs[i + 1:i + 13:2]:
+            reg, lit = re.match(r"s_add_u32 s(\d+), s82, (0x[0-9a-f]+)", ins[a]).groups()
+            base[int(reg)] = gp[0] + 4 + int(lit, 16)
+        for h, W in ((base[84], 36), (base[86], 52)):
+            assert h % 512 == 0
+            for kind in range(8):
+                want = "s_branch" if kind >= 6 else "s_bfe_u32 s74, s%d, 0x7000c" % W
+                assert ins.get(h + 512 * kind, "").startswith(want), (name, kind)
+        for r, W in ((base[88], 36), (base[90], 52)):
+            for step in range(14):
+                assert ins.get(r + 20 * step) == "s_set_gpr_idx_on s%d, gpr_idx(SRC0,DST)" % (W + 15 - step)
+            assert ins.get(r + 280) == "s_set_gpr_idx_off"
+        for k in range(K):
+            assert ins.get(base[92] + 16 * k, "").startswith("global_load_dwordx4 v[%d:%d]" % (4 + 4 * k, 7 + 4 * k))
+        for k in range(64):
+            assert ins.get(base[94] + 8 * k, "").startswith("s_waitcnt vmcnt(%d)" % k)

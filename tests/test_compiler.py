@@ -130,7 +130,7 @@ def test_paper_matrix_stages_equal_oracle():
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
-@pytest.mark.parametrize("K", [16, 24, 32, 40, 48])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
 def test_bytecode_simulates_to_bitmatrix(level, K):
     n, p = 10, 4
     gen = E.ec_matrix_cauchy(n, p)
@@ -139,28 +139,44 @@ def test_bytecode_simulates_to_bitmatrix(level, K):
         rows = oracle_rows(gen, n, p, er)
         stmts, outs = prog.export(E.STAGE_EXEC)
         assert eval_export(stmts, outs) == rows
-        got = simulate(prog.bytecode(), K, 8 * n, 8 * len(prog.out_blocks))
+        got = simulate(prog.bytecode(), K, n, len(prog.out_blocks))
         assert [got[o] for o in range(len(rows))] == rows
         assert prog.info["n_stores"] == len(rows)
+        assert prog.info["slots"] == K
+        assert prog.info["n_loads"] == 80 * prog.info["passes"]
 
 
 @pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])
 def test_bytecode_other_codecs(n, p):
     gen = E.ec_matrix_cauchy(n, p)
     for er in sample_patterns(n, p, 3, 7 * n):
-        prog = E.ec_compile_slp(n, p, gen, er, slot_budget=32)
-        rows = oracle_rows(gen, n, p, er)
-        got = simulate(prog.bytecode(), 32, 8 * n, 8 * len(prog.out_blocks))
-        assert [got[o] for o in range(len(rows))] == rows
+        for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+            prog = E.ec_compile_slp(n, p, gen, er, level=level)
+            rows = oracle_rows(gen, n, p, er)
+            got = simulate(prog.bytecode(), prog.info["slots"], n, len(prog.out_blocks))
+            assert [got[o] for o in range(len(rows))] == rows
 
 
-def test_hoist_option_keeps_semantics():
+def test_wide_codec_needs_row_passes():
+    # 8 parity blocks = 64 rows: more than the slots, so the inputs stream
+    # through once per group of output blocks
+    n, p = 8, 8
+    gen = E.ec_matrix_cauchy(n, p)
+    for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+        prog = E.ec_compile_slp(n, p, gen, level=level, slot_budget=48)
+        assert prog.info["passes"] >= 2
+        rows = oracle_rows(gen, n, p)
+        got = simulate(prog.bytecode(), 48, n, p, tiles=3)
+        assert [got[o] for o in range(64)] == rows
+
+
+@pytest.mark.parametrize("width", [1, 4, 8, 16, 40])
+def test_block_width_option_keeps_semantics(width):
     gen = E.ec_matrix_cauchy(10, 4)
     rows = oracle_rows(gen, 10, 4)
-    for h in (1, 4, 64, 1000):
-        prog = E.ec_compile_slp(10, 4, gen, hoist=h, slot_budget=32)
-        got = simulate(prog.bytecode(), 32, 80, 32)
-        assert [got[o] for o in range(32)] == rows
+    prog = E.ec_compile_slp(10, 4, gen, block_strips=width, slot_budget=48)
+    got = simulate(prog.bytecode(), 48, 10, 4)
+    assert [got[o] for o in range(32)] == rows
 
 
 def test_compressed_beats_plain_in_xors():
@@ -168,6 +184,10 @@ def test_compressed_beats_plain_in_xors():
     plain = E.ec_compile_slp(10, 4, gen, level=E.LEVEL_PLAIN)
     co = E.ec_compile_slp(10, 4, gen)
     assert co.info["n_xor2"] < plain.info["n_xor2"] == 1256
+    # the executor's unit of work: one slot XOR (plain: every 1 bit, plus
+    # clearing the 32 row slots after their store)
+    assert plain.info["n_ops"] == 1288 + 32
+    assert co.info["n_ops"] < 0.75 * plain.info["n_ops"]
 
 
 def test_compile_errors():
@@ -189,6 +209,9 @@ def test_compile_errors():
     with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(10, 4, gen, slot_budget=20)
     assert e.value.name == "EC_ERR_UNSUPPORTED"
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, gen, block_strips=81)
+    assert e.value.name == "EC_ERR_ARG"
     with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
     assert e.value.name == "EC_ERR_ARG"

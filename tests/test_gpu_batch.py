@@ -39,8 +39,8 @@ def check(outs, want, what):
             assert np.array_equal(a.cpu().numpy(), b), "%s: stripe %d output %d" % (what, k, j)
 
 
-@pytest.mark.parametrize("level,slots,tile", [(E.LEVEL_PLAIN, 40, 0), (E.LEVEL_PLAIN, 48, 4096),
-                                              (E.LEVEL_CO_FU_SCHED, 48, 0)])
+@pytest.mark.parametrize("level,slots,tile", [(E.LEVEL_PLAIN, 38, 0), (E.LEVEL_PLAIN, 48, 4096),
+                                              (E.LEVEL_CO_FU_SCHED, 44, 0), (E.LEVEL_CO_FU_SCHED, 24, 2048)])
 def test_batch_mixed_matches_oracle_and_graph_replays(level, slots, tile):
     specs = B.mixed_specs(96, seed=5, lo=4096, hi=64 * 1024)
     cache = B.ProgramCache(level=level, slots=slots)

@@ -68,7 +68,7 @@ def compile_many(n, p, gen, patterns, **kw):
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
-@pytest.mark.parametrize("K", [16, 24, 32, 40, 48])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
 def test_encode_rs10_4_1mib(level, K):
     """RS(10,4) encode, 10 x 1 MiB blocks of seeded random bytes."""
     n, p, S = 10, 4, 1 << 20
@@ -98,6 +98,23 @@ def test_encode_other_codecs(n, p):
     for K in (24, 48):
         prog = E.ec_compile_slp(n, p, gen, slot_budget=K)
         assert_blocks_equal(run_encode(prog, data, S), want, "RS(%d,%d) K %d" % (n, p, K))
+
+
+def test_encode_row_passes_and_block_widths():
+    """RS(8,8) needs several passes over the inputs (64 rows > slots);
+    RS(10,4) with other column-block widths."""
+    S = 64 * 1024 + 128
+    gen = E.ec_matrix_cauchy(8, 8)
+    data = W.host_blocks(8, S, seed=88)
+    want = oracle.encode(np.array(gen, dtype=np.uint8), 8, 8, data)
+    for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+        prog = E.ec_compile_slp(8, 8, gen, level=level, slot_budget=48)
+        assert prog.info["passes"] >= 2
+        assert_blocks_equal(run_encode(prog, data, S), want, "RS(8,8) level %d" % level)
+    gen, data, want = rs10_4_1mib()
+    for width in (1, 4, 16, 40):
+        prog = E.ec_compile_slp(10, 4, gen, block_strips=width, slot_budget=48)
+        assert_blocks_equal(run_encode(prog, data, 1 << 20), want, "width %d" % width)
 
 
 def all_patterns(n, p):
