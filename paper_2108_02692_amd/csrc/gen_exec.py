@@ -187,6 +187,17 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 static_assert(bc::kMaxOps == %(MAX_OPS)d && bc::kRunStepBytes == %(STEP)d && bc::kMaxWait == %(MAXW)d,
               "record format and executor tables disagree");
 
+// Lane b of the result: block b's pointer plus the tile offset.  The
+// executor reads it from any lane with v_readlane, also in a ragged last
+// tile where only the lanes below the strip's end are active, so it must be
+// computed with every lane on: a volatile asm statement is never moved into
+// the partial-tile branch.
+__device__ __forceinline__ uint64_t tile_table(uint64_t tab, uint64_t toff) {
+  uint64_t t;
+  asm volatile("v_lshl_add_u64 %%0, %%1, 0, %%2" : "=v"(t) : "s"(toff), "v"(tab));
+  return t;
+}
+
 typedef const __attribute__((address_space(4))) StripeDesc *ConstDescPtr;
 typedef const __attribute__((address_space(4))) uint32_t *ConstU32Ptr;
 
@@ -218,7 +229,7 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
   EC_INIT_%(K)d;
   for (uint32_t tile = wave; tile < a.n_tiles; tile += n_waves) {
     const uint64_t toff = (uint64_t)tile * kTileBytes;
-    const uint64_t t = tab + toff;
+    const uint64_t t = tile_table(tab, toff);
     const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
     if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
   }
@@ -246,7 +257,7 @@ __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
     for (uint32_t k = 0; k < a.tiles_per_item; ++k) {
       const uint64_t toff = (uint64_t)(tile + k) * kTileBytes;
       if (toff >= sl) break;
-      const uint64_t t = tab + toff;
+      const uint64_t t = tile_table(tab, toff);
       const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
       if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
     }

@@ -515,10 +515,10 @@ int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushC
     ring_min = std::min(ring_min, ring);
     if (run_pass(ps, n_in_blocks, ring, m, peak_open, n_ops) < 0) return -1;
   }
-  // Leave every slot whose first use is as an accumulator zero again for the
-  // next tile.
+  // Leave every slot zero: the next tile may run another program (a batch
+  // mixes them), and every program starts from all-zero slots.
   for (int s = 0; s < K; ++s)
-    if (m.state[s] == FREE_DIRTY && m.first_use[s] == 1) m.recs[m.last_pull[s]].ops.push_back(s);
+    if (m.state[s] == FREE_DIRTY) m.recs[m.last_pull[s]].ops.push_back(s);
 
   // Encode; runs longer than one record continue in RUN records.
   std::vector<uint32_t> &w = out.words;
@@ -656,7 +656,7 @@ bool simulate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
     for (size_t r = 0; r < rows.size(); ++r)
       if (!written[r] || !(out[r] == rows[r])) return false;
     for (int s = 0; s < slots; ++s)
-      if (busy[s]) return false;  // every load was consumed within the tile
+      if (busy[s] || !(slot[s] == Bits())) return false;  // loads consumed, slots left zero
   }
   return true;
 }

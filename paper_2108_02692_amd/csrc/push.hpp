@@ -89,8 +89,9 @@ bool validate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
 // Runs a record stream on set-valued slots for two consecutive tiles (from
 // all-zero slots; the second tile starts from the state the first leaves)
 // and checks that every output strip of both equals `rows`, that no slot is
-// read before its load has been waited for, and that no load lands in a
-// slot that is still being read or accumulated.
+// read before its load has been waited for, that no load lands in a slot
+// that is still being read or accumulated, and that every slot is zero again
+// at the end of a tile.
 bool simulate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, int n_out_blocks,
                    const std::vector<Bits> &rows);
 

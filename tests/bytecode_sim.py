@@ -7,7 +7,8 @@ a load lands only when a WAIT retires it (in issue order, stores included),
 so reading or accumulating into a slot whose load may still be in flight is
 an error, as is loading into such a slot.  The program is run for several
 consecutive tiles from all-zero slots, each tile starting from the state the
-previous one left, and every tile must store the same values.
+previous one left, and every tile must store the same values and leave
+every slot zero (the next tile may run another program).
 """
 
 KINDS = {0: "RUN", 1: "INPUT", 2: "INPUT_LD", 3: "VALUE", 4: "STORE", 5: "LOAD", 6: "HALT"}
@@ -97,6 +98,7 @@ def simulate(words, slots, n_in_blocks, n_out_blocks, tiles=2):
                 val[s] ^= acc
             pc += 2 + n
         check(not any(busy), "load left unconsumed")
+        check(not any(val), "a slot is not zero at the end of the tile")
         if first is None:
             first = out
         else:

@@ -185,8 +185,9 @@ def test_compressed_beats_plain_in_xors():
     co = E.ec_compile_slp(10, 4, gen)
     assert co.info["n_xor2"] < plain.info["n_xor2"] == 1256
     # the executor's unit of work: one slot XOR (plain: every 1 bit, plus
-    # clearing the 32 row slots after their store)
-    assert plain.info["n_ops"] == 1288 + 32
+    # clearing the 32 row slots after their store and the ring slots at the
+    # end of the tile)
+    assert 1288 + 32 <= plain.info["n_ops"] <= 1288 + 32 + plain.info["ring"]
     assert co.info["n_ops"] < 0.75 * plain.info["n_ops"]
 
 
