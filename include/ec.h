@@ -74,9 +74,10 @@ enum { EC_COMPRESS_XORREPAIR = 0, EC_COMPRESS_REPAIR = 1 };
 typedef struct {
   uint32_t level;        /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
   uint32_t slot_budget;  /* register slots per lane (16 B each); supported: 24, 32, 36, 38, 40,
-                            44, 48; 0 = default: the smallest supported budget that holds
-                            all output rows (one pass over the inputs), the open
-                            temporaries and a ring of 6 strip loads (48 if none does) */
+                            44, 48 (the executor runs 4 waves per SIMD up to 24 slots, 3 up to
+                            38, else 2); 0 = default: the first of 24, 32, 38, 44, 48 that holds
+                            every output row in one pass over the inputs with a ring of at
+                            least 3 strip loads (48 if none does) */
   uint32_t compress;     /* EC_COMPRESS_*; default XorRePair */
   uint32_t block_strips; /* width in strips of the column blocks compressed separately
                             (levels >= CO); 0 = 8, one data block; 8*n = the whole matrix */

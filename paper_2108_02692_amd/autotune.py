@@ -15,8 +15,8 @@ from . import LEVEL_CO_FU_SCHED, LEVEL_PLAIN
 from .batching import ProgramCache, build_batch
 
 DEFAULT_CANDIDATES = (
-    (LEVEL_CO_FU_SCHED, 38, 1024), (LEVEL_CO_FU_SCHED, 44, 1024), (LEVEL_CO_FU_SCHED, 44, 4096),
-    (LEVEL_CO_FU_SCHED, 44, 16384), (LEVEL_PLAIN, 38, 1024), (LEVEL_PLAIN, 44, 4096),
+    (LEVEL_CO_FU_SCHED, 38, 1024), (LEVEL_CO_FU_SCHED, 38, 4096), (LEVEL_CO_FU_SCHED, 38, 16384),
+    (LEVEL_CO_FU_SCHED, 44, 1024), (LEVEL_PLAIN, 38, 1024), (LEVEL_PLAIN, 38, 4096),
 )
 CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 

@@ -167,17 +167,37 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
       po.slots = (int)o.slot_budget;
       return push_schedule(dag, n_in, po, prog->code);
     }
-    // smallest budget with one pass over the inputs and a ring of 6 loads
-    // beside the rows and the open temporaries
+    // The budgets that set the executor's occupancy (4, 3 and 2 waves per
+    // SIMD for 24, 38 and 48 slots; 32 and 44 in between), smallest first:
+    // the first that holds every row in one pass over the inputs with a ring
+    // of at least 3 loads.
     int rc = -1;
-    for (uint32_t k : kSlotBudgets) {
+    for (uint32_t k : {24u, 32u, 38u, 44u, 48u}) {
       po.slots = (int)k;
       rc = push_schedule(dag, n_in, po, prog->code);
-      if (rc == 0 && ((prog->code.passes == 1 && prog->code.ring >= 6) || k == 48)) break;
+      if (rc == 0 && ((prog->code.passes == 1 && prog->code.ring >= 3) || k == 48)) break;
     }
     return rc;
   };
   int rc = place();
+  // By default, a few more unfolded temporaries are worth it when they let
+  // the program run at 3 waves per SIMD (38 slots) instead of 2.
+  if (rc == 0 && !o.slot_budget && po.slots > 38 && o.level >= EC_LEVEL_CO_FU_SCHED && n_out * 8 <= 32) {
+    for (int cost : {3, 4, 6}) {
+      PushDag trial = dag;
+      push_unfold(trial, cost);
+      push_order(trial, width);
+      PushCode code;
+      PushOpts p38;
+      p38.slots = 38;
+      if (push_schedule(trial, n_in, p38, code) == 0 && code.passes == 1 && code.ring >= 3) {
+        dag = trial;
+        prog->code = code;
+        po = p38;
+        break;
+      }
+    }
+  }
   // Too many temporaries open for the budget: unfold more of them (in the
   // limit every temporary is inlined and none is open) until it fits.
   for (int cost : {4, 8, 16, 64, 1 << 20}) {

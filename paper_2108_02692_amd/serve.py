@@ -86,7 +86,7 @@ class Server:
     """Admission by HBM budget, ``n_slots`` batches in flight, each on its own
     stream with a reusable ``ec_batch``."""
 
-    def __init__(self, budget_bytes=16 << 30, n_slots=4, max_batch=512, level=LEVEL_CO_FU_SCHED, slots=44,
+    def __init__(self, budget_bytes=16 << 30, n_slots=4, max_batch=512, level=LEVEL_CO_FU_SCHED, slots=38,
                  tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True):
         import torch
         self.torch = torch
