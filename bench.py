@@ -6,8 +6,8 @@ seeded uniform random bytes (640 MiB in), 4 parity blocks (256 MiB out), each
 block split into 8 contiguous strips.  One step = one ec_encode launch over
 the whole stripe with inputs resident in HBM.  The headline value is the
 compressed + fused + scheduled program; the plain bitmatrix program, a
-4-erasure decode, and a plain device copy run on the same data for
-comparison.
+4-erasure decode and a plain device copy run on the same data for comparison,
+followed by the batched and the serving workloads and the oracle on the host.
 
 Prints one JSON line (see the keys below).  ``--gpus`` above 1 is refused:
 this build runs on one GPU.
@@ -15,8 +15,10 @@ this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +27,7 @@ sys.path.insert(0, HERE)
 
 METRIC = "encode/decode GB/s (input bytes) and % HBM roofline, compressed SLP vs plain bitmatrix"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PROFILES = os.path.join(HERE, "profiles")
 
 
 def parse():
@@ -33,11 +36,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--block-mib", type=int, default=64)
-    ap.add_argument("--slots", type=int, default=0, help="register slot budget (0 = library default)")
+    ap.add_argument("--slots", type=int, default=0, help="slot budget of the compressed program (0 = default)")
+    ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
-    ap.add_argument("--only", choices=["all", "compressed", "plain"], default="all")
-    ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = --slots)")
+    ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy"], default="all",
+                    help="time one kernel only (for profiler runs)")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run one device copy of 448 MiB (byte-counter calibration)")
     ap.add_argument("--batch-stripes", type=int, default=8192, help="stripes in the batched workload (0 = skip)")
     ap.add_argument("--batch-max-mib", type=int, default=4, help="largest block of the batched workload (MiB)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of Poisson arrivals (0 = skip)")
@@ -47,7 +53,13 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print("bench.py: %s" % msg, file=sys.stderr, flush=True)
+
+
 def time_launches(fn, steps, warmup, stream):
+    """Average ms per launch over `steps` back-to-back launches, bracketed by
+    HIP events on the stream the kernels run on."""
     import torch
     for _ in range(warmup):
         fn()
@@ -59,11 +71,37 @@ def time_launches(fn, steps, warmup, stream):
         fn()
     end.record(stream)
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps  # ms per launch
+    return start.elapsed_time(end) / steps
 
 
-def log(msg):
-    print("bench.py: %s" % msg, file=sys.stderr, flush=True)
+def sha256_file(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def program_sha(prog):
+    import struct
+    w = prog.bytecode()
+    return hashlib.sha256(struct.pack("<%dI" % len(w), *w)).hexdigest()
+
+
+def measured_traffic(prog):
+    """HBM bytes per launch from the committed byte-counter profile of this
+    workload, if it was taken on this executor and this program (else None)."""
+    import paper_2108_02692_amd
+    exec_sha = sha256_file(os.path.join(os.path.dirname(paper_2108_02692_amd.__file__), "csrc", "exec.hip"))
+    psha = program_sha(prog)
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            for m in re.finditer(r"<!-- traffic (\{.*?\}) -->", f.read()):
+                rec = json.loads(m.group(1))
+                if rec.get("exec_hip_sha256") == exec_sha and rec.get("program_sha256") == psha:
+                    return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
 
 
 def main():
@@ -72,7 +110,6 @@ def main():
         print("bench.py: this build runs on one GPU only (--gpus %d refused); "
               "multi-GPU sharding is described in DESIGN.md" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_2108_02692_amd as E
     from paper_2108_02692_amd import workloads as W
@@ -94,13 +131,14 @@ def main():
     def measure(prog, ins, outs, decode=False):
         f = (lambda: E.ec_decode(prog, ins, outs, S, stream)) if decode else \
             (lambda: E.ec_encode(prog, ins, outs, S, stream))
-        ms = time_launches(f, args.steps, args.warmup, stream)
-        return ms
+        return time_launches(f, args.steps, args.warmup, stream)
 
     t0 = time.time()
     comp = E.ec_compile_slp(n, p, gen, level=E.LEVEL_CO_FU_SCHED, slot_budget=args.slots)
     compile_ms = (time.time() - t0) * 1e3
-    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots or args.slots)
+    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots)
+    log("compiled (compressed %.0f ms, %d slots; plain %d slots)" % (compile_ms, comp.info["slots"],
+                                                                     plain.info["slots"]))
     if args.sweep:
         for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
             for K in (24, 32, 36, 38, 40, 44, 48):
@@ -112,7 +150,6 @@ def main():
                                   "ring": pr.info["ring"], "open": pr.info["peak_open"]}), flush=True)
         return
 
-    log("compiled (compressed %.0f ms)" % compile_ms)
     res = {}
     if args.only in ("all", "compressed"):
         res["compressed"] = measure(comp, data, parity)
@@ -120,10 +157,10 @@ def main():
         res["plain"] = measure(plain, data, parity)
     log("encode timed: %s" % res)
     extra = {}
-    if args.only == "all":
-        # decode of the worst 4-erasure set of data blocks (4 data blocks lost)
+    if args.only in ("all", "decode"):
+        # decode of 4 lost data blocks (the paper's decode example erases 4)
         er = [2, 4, 5, 6]
-        dprog = E.ec_compile_slp(n, p, gen, er, slot_budget=args.slots)
+        dprog = E.ec_compile_slp(n, p, gen, er)
         blocks = data + parity
         E.ec_encode(comp, data, parity, S, stream)
         surv = [blocks[i] for i in dprog.in_blocks]
@@ -135,25 +172,37 @@ def main():
                 raise SystemExit("bench.py: decode self-check failed for block %d" % e)
         dmoved = (n + len(er)) * S
         extra["decode"] = {"erased": er, "ms": ms_dec, "GB_s": in_bytes / ms_dec / 1e6,
-                           "hbm_frac": dmoved / ms_dec / 1e6 / HBM_PEAK_GBS,
-                           "n_xor2": dprog.info["n_xor2"], "plain_xor2": dprog.info["plain_xor2"]}
+                           "hbm_frac": dmoved / ms_dec / 1e6 / HBM_PEAK_GBS, "slots": dprog.info["slots"],
+                           "n_xor2": dprog.info["n_xor2"], "plain_xor2": dprog.info["plain_xor2"],
+                           "ops_per_tile": dprog.info["n_ops"]}
         del rec
+    if args.only in ("all", "copy") or args.calib:
         # plain device copy of the same number of bytes (read + write = moved)
         src = torch.empty(moved // 2, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
-        ms_copy = time_launches(lambda: E.ec_device_copy(dst, src, src.numel(), stream), args.steps,
-                                args.warmup, stream)
-        extra["copy_ceiling_GB_s"] = 2 * src.numel() / ms_copy / 1e6
+        copy = (lambda: E.ec_device_copy(dst, src, src.numel(), stream))
+        if args.only in ("all", "copy"):
+            ms_copy = time_launches(copy, args.steps, args.warmup, stream)
+            extra["copy_ceiling_GB_s"] = 2 * src.numel() / ms_copy / 1e6
+        else:
+            copy()
+            torch.cuda.synchronize()
         del src, dst
+    if args.only == "copy":
+        print(json.dumps(extra), flush=True)
+        return
+    if args.only == "decode":
+        print(json.dumps(extra), flush=True)
+        return
 
     head = "compressed" if "compressed" in res else "plain"
+    hprog = comp if head == "compressed" else plain
     ms = res[head]
-    gbs = in_bytes / ms / 1e6
     achieved = moved / ms / 1e6
-    info = (comp if head == "compressed" else plain).info
+    info = hprog.info
     out = {
         "metric": METRIC,
-        "value": gbs,
+        "value": in_bytes / ms / 1e6,
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -177,7 +226,8 @@ def main():
             "compile_ms": compile_ms,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(hprog),
+                     "kernel": "slp_exec_kernel_%d" % info["slots"]},
     }
     if "plain" in res and head == "compressed":
         pms = res["plain"]
@@ -252,7 +302,6 @@ def bench_batched(args, stream):
 
 def cpu_baseline(block_mib: int):
     """The oracle, as is, on a bounded sample of the same workload."""
-    import numpy as np
     import oracle
     from paper_2108_02692_amd import workloads as W
     S = block_mib << 20
