@@ -141,13 +141,15 @@ def main():
                                                                      plain.info["slots"]))
     if args.sweep:
         for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
-            for K in (24, 32, 36, 38, 40, 44, 48):
-                pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K)
-                ms = measure(pr, data, parity)
-                print(json.dumps({"sweep": True, "level": level, "slots": K, "ms": ms, "GB_s": in_bytes / ms / 1e6,
-                                  "hbm_frac": moved / ms / 1e6 / HBM_PEAK_GBS, "n_xor2": pr.info["n_xor2"],
-                                  "ops": pr.info["n_ops"], "records": pr.info["n_records"],
-                                  "ring": pr.info["ring"], "open": pr.info["peak_open"]}), flush=True)
+            for K in (32, 36, 38, 40, 44, 48):
+                for dist in (0, 4, 8, 12, 20):
+                    pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K, prefetch=dist)
+                    ms = measure(pr, data, parity)
+                    print(json.dumps({"sweep": True, "level": level, "slots": K, "prefetch": dist, "ms": ms,
+                                      "GB_s": in_bytes / ms / 1e6, "hbm_frac": moved / ms / 1e6 / HBM_PEAK_GBS,
+                                      "n_xor2": pr.info["n_xor2"], "ops": pr.info["n_ops"],
+                                      "records": pr.info["n_records"], "ring": pr.info["ring"],
+                                      "open": pr.info["peak_open"]}), flush=True)
         return
 
     res = {}

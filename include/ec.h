@@ -81,6 +81,9 @@ typedef struct {
   uint32_t compress;     /* EC_COMPRESS_*; default XorRePair */
   uint32_t block_strips; /* width in strips of the column blocks compressed separately
                             (levels >= CO); 0 = 8, one data block; 8*n = the whole matrix */
+  uint32_t prefetch;     /* distance in strips at which strips are touched (4 B per lane)
+                            ahead of their register load, so that the load finds them in
+                            the L2 cache; 0 = none (NULL opts: the library's default) */
 } ec_compile_opts;
 
 typedef struct {

@@ -39,9 +39,15 @@ class EcError(RuntimeError):
         super().__init__("%s: %s (%s)" % (what, self.name, ec_status_str(status)))
 
 
+# L2 prefetch distance (strips) used when none is given (the library's own
+# default for NULL options is the same).
+DEFAULT_PREFETCH = 0
+
+
 class CompileOpts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("slot_budget", ctypes.c_uint32),
-                ("compress", ctypes.c_uint32), ("block_strips", ctypes.c_uint32)]
+                ("compress", ctypes.c_uint32), ("block_strips", ctypes.c_uint32),
+                ("prefetch", ctypes.c_uint32)]
 
 
 class ProgramInfo(ctypes.Structure):
@@ -213,10 +219,12 @@ class Program:
 
 
 def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
-                   compress: int = COMPRESS_XORREPAIR, block_strips: int = 0) -> Program:
+                   compress: int = COMPRESS_XORREPAIR, block_strips: int = 0,
+                   prefetch: int | None = None) -> Program:
     er = list(erased)
     er_arr = (ctypes.c_int * max(1, len(er)))(*er)
-    opts = CompileOpts(level, slot_budget, compress, block_strips)
+    opts = CompileOpts(level, slot_budget, compress, block_strips,
+                       DEFAULT_PREFETCH if prefetch is None else prefetch)
     h = ctypes.c_void_p()
     _check(lib().ec_compile_slp(n, p, _flat_gen(gen, n, p), er_arr, len(er), ctypes.byref(opts), ctypes.byref(h)),
            "ec_compile_slp")

@@ -13,6 +13,9 @@
 //   VALUE      -     x    -     -
 //   STORE      -     x    -     x
 //   LOAD       -     -    x     -
+//   PREFETCH   (no register: 4 B per lane of strip (blk, j) into a scratch
+//              register, so that the strip's lines are in the L2 cache when
+//              its real load comes; counts as a memory operation for WAIT)
 //   HALT       end of the program
 //
 //   WAIT   s_waitcnt vmcnt(wait): the pulled slot's load has landed
@@ -36,7 +39,7 @@
 namespace ec {
 namespace bc {
 
-enum Kind : uint32_t { RUN = 0, INPUT = 1, INPUT_LD = 2, VALUE = 3, STORE = 4, LOAD = 5, HALT = 6 };
+enum Kind : uint32_t { RUN = 0, INPUT = 1, INPUT_LD = 2, VALUE = 3, STORE = 4, LOAD = 5, HALT = 6, PREFETCH = 7 };
 
 constexpr int kMaxOps = 14;       // operands per record
 constexpr int kWindow = 16;       // words the executor reads per record

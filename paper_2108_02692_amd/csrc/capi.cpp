@@ -27,6 +27,9 @@ constexpr uint32_t kSlotBudgets[] = {24, 32, 36, 38, 40, 44, 48};  // executor k
 // of a temporary (one record against the XORs it saves).
 constexpr int kRecordCost = 2;
 
+// L2 prefetch distance (strips) of programs compiled with the defaults.
+constexpr uint32_t kDefaultPrefetch = 0;
+
 bool supported_slots(uint32_t k) {
   for (uint32_t s : kSlotBudgets)
     if (s == k) return true;
@@ -116,11 +119,11 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     for (int j = 0; j < i; ++j)
       if (erased[j] == erased[i]) return EC_ERR_ARG;
   }
-  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0};
+  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0, kDefaultPrefetch};
   if (opts) o = *opts;
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
-  if (o.block_strips > (uint32_t)(8 * n)) return EC_ERR_ARG;
+  if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -162,6 +165,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     }
   }
   PushOpts po;
+  po.prefetch = (int)o.prefetch;
   auto place = [&]() -> int {
     if (o.slot_budget) {
       po.slots = (int)o.slot_budget;
@@ -188,7 +192,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
       push_unfold(trial, cost);
       push_order(trial, width);
       PushCode code;
-      PushOpts p38;
+      PushOpts p38 = po;
       p38.slots = 38;
       if (push_schedule(trial, n_in, p38, code) == 0 && code.passes == 1 && code.ring >= 3) {
         dag = trial;

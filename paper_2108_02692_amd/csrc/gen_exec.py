@@ -36,11 +36,15 @@ def operands(K, mode):
     ops = ['"%s{v[0:3]}"(acc)' % c]
     for i, (lo, size) in enumerate(groups(K)):
         ops.append('"%s{v[%d:%d]}"(g%d)' % (c, lo, lo + size - 1, i))
+    # the prefetch target: written by loads that may still be in flight when
+    # an asm statement ends, so pinned like the slots and never used
+    ops.append('"%s{v%d}"(junk)' % (c, 4 + 4 * K))
     return ", ".join(ops)
 
 
 def decls(K):
-    return "v4u acc;\n  " + " ".join("%s g%d;" % (vtype(size), i) for i, (lo, size) in enumerate(groups(K)))
+    return "v4u acc;\n  uint32_t junk;\n  " + " ".join("%s g%d;" % (vtype(size), i)
+                                                      for i, (lo, size) in enumerate(groups(K)))
 
 
 def asm_lines(lines):
@@ -97,7 +101,7 @@ def handler(K, kind, W, O, run_base, h_other):
         4: nxt + pull + addr + store + run,
         5: nxt + addr + ld + run,
         6: ["s_branch 99f"],
-        7: ["s_branch 99f"],
+        7: nxt + addr + ["global_load_dword v%d, %%[voff], s[72:73]" % (4 + 4 * K)] + run,
     }[kind]
     return [".p2align 9"] + body
 
@@ -305,7 +309,7 @@ int copy_launch(const void *src, void *dst, size_t bytes, hipStream_t stream) {
 
 
 def init_asm(K):
-    regs = ["v_mov_b32_e32 v%d, 0" % r for r in range(4 + 4 * K)]
+    regs = ["v_mov_b32_e32 v%d, 0" % r for r in range(4 + 4 * K + 1)]
     return '"' + "\\n\\t".join(regs) + '"'
 
 

@@ -333,7 +333,7 @@ struct Pass {
 
 // One pass: every output row accumulates in its own slot while all strips
 // stream through.  Returns -1 if a slot is not available.
-int run_pass(const Pass &ps, int n_in_blocks, int ring, Machine &m, int &peak_open, int &n_ops) {
+int run_pass(const Pass &ps, int n_in_blocks, int ring, int prefetch, Machine &m, int &peak_open, int &n_ops) {
   const PushDag &d = ps.d;
   const int R = d.n_rows;
   const std::vector<std::vector<int>> cons = consumers(d);
@@ -357,6 +357,19 @@ int run_pass(const Pass &ps, int n_in_blocks, int ring, Machine &m, int &peak_op
     ++next_load;
     return 0;
   };
+  // Prefetches run `prefetch` strips ahead of the register loads.
+  size_t next_pf = 0;
+  auto prefetch_upto = [&](size_t upto) {
+    for (; next_pf < std::min(upto, d.order.size()); ++next_pf) {
+      if (next_pf < next_load) continue;  // already loaded
+      Rec pf;
+      pf.kind = bc::PREFETCH;
+      pf.blk = d.order[next_pf] / 8;
+      pf.j = d.order[next_pf] % 8;
+      pf.ld_seq = m.vm_seq++;
+      m.recs.push_back(pf);
+    }
+  };
   // prologue: fill the ring
   while (next_load < d.order.size() && (int)(next_load - loaded) < ring) {
     Rec rec;
@@ -364,6 +377,7 @@ int run_pass(const Pass &ps, int n_in_blocks, int ring, Machine &m, int &peak_op
     if (issue(rec) < 0) return -1;
     m.recs.push_back(rec);
   }
+  if (prefetch > 0) prefetch_upto(next_load + prefetch);
   // Run of the value held in the accumulator (pulled from slot `from`):
   // one XOR per consuming accumulator, opening temporaries as needed.
   // Temporaries it completes are appended to `done`.
@@ -427,6 +441,7 @@ int run_pass(const Pass &ps, int n_in_blocks, int ring, Machine &m, int &peak_op
     }
     n_ops += (int)rec.ops.size();
     m.recs.push_back(rec);
+    if (prefetch > 0) prefetch_upto(next_load + prefetch);
     if (finish(done) < 0) return -1;
   }
   for (int r = 0; r < R; ++r) {
@@ -513,7 +528,7 @@ int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushC
   for (const Pass &ps : passes) {
     const int ring = std::min(opts.max_ring, K - ps.d.n_rows - peak_open_temps(ps.d));
     ring_min = std::min(ring_min, ring);
-    if (run_pass(ps, n_in_blocks, ring, m, peak_open, n_ops) < 0) return -1;
+    if (run_pass(ps, n_in_blocks, ring, opts.prefetch, m, peak_open, n_ops) < 0) return -1;
   }
   // Leave every slot zero: the next tile may run another program (a batch
   // mixes them), and every program starts from all-zero slots.
@@ -524,6 +539,7 @@ int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushC
   std::vector<uint32_t> &w = out.words;
   w.clear();
   int vm_issued = 0, n_records = 0, n_loads = 0, n_stores = 0;
+  out.n_prefetch = 0;
   for (const Rec &rec : m.recs) {
     uint32_t wait = 0;
     if (rec.kind == bc::INPUT || rec.kind == bc::INPUT_LD)
@@ -534,8 +550,9 @@ int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushC
       const size_t n = std::min<size_t>(bc::kMaxOps, rec.ops.size() - k);
       const uint32_t kind = first ? rec.kind : (uint32_t)bc::RUN;
       const bool has_ld = first && (kind == bc::INPUT_LD || kind == bc::LOAD);
-      const bool has_blk = has_ld || (first && kind == bc::STORE);
-      const uint32_t pull = (first && kind != bc::LOAD && kind != bc::RUN) ? (uint32_t)rec.pull : 0u;
+      const bool has_blk = has_ld || (first && (kind == bc::STORE || kind == bc::PREFETCH));
+      const uint32_t pull =
+          (first && kind != bc::LOAD && kind != bc::RUN && kind != bc::PREFETCH) ? (uint32_t)rec.pull : 0u;
       w.push_back(bc::h0(kind, pull, (uint32_t)n));
       w.push_back(bc::h1(first ? wait : 0u, has_ld ? (uint32_t)rec.ld_slot : 0u, has_blk ? (uint32_t)rec.blk : 0u,
                          has_blk ? (uint32_t)rec.j : 0u));
@@ -546,6 +563,7 @@ int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushC
     } while (k < rec.ops.size());
     if (rec.kind == bc::INPUT_LD || rec.kind == bc::LOAD) { ++vm_issued; ++n_loads; }
     if (rec.kind == bc::STORE) { ++vm_issued; ++n_stores; }
+    if (rec.kind == bc::PREFETCH) { ++vm_issued; ++out.n_prefetch; }
   }
   w.push_back(bc::h0(bc::HALT, 0, 0));
   w.push_back(0);
@@ -571,7 +589,6 @@ bool validate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
     if (pc + bc::kWindow > w.size()) return false;
     const uint32_t a = w[pc], b = w[pc + 1];
     const uint32_t kind = bc::h0_kind(a);
-    if (kind > bc::HALT) return false;
     if (kind == bc::HALT) {
       if (a != bc::h0(bc::HALT, 0, 0) || b != 0) return false;
       for (size_t q = pc + 2; q < w.size(); ++q)
@@ -593,7 +610,8 @@ bool validate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
     if (lds && ((int)ld >= slots || (int)blk >= n_in_blocks)) return false;
     if (!lds && ld) return false;
     if (kind == bc::STORE && ((int)blk < n_in_blocks || (int)blk >= n_in_blocks + n_out_blocks)) return false;
-    if (!lds && kind != bc::STORE && (blk || j)) return false;
+    if (kind == bc::PREFETCH && ((int)blk >= n_in_blocks || n)) return false;
+    if (!lds && kind != bc::STORE && kind != bc::PREFETCH && (blk || j)) return false;
     if (pc + 2 + n > w.size()) return false;
     for (uint32_t q = 0; q < n; ++q) {
       const uint32_t o = w[pc + 2 + q];
@@ -640,6 +658,7 @@ bool simulate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
         busy[s] = 1;
         vm.push_back(s);
       }
+      if (kind == bc::PREFETCH) vm.push_back(-1);
       if (kind == bc::STORE) {
         const int o = 8 * ((int)bc::h1_blk(b) - n_in_blocks) + (int)bc::h1_j(b);
         out[o] = acc;

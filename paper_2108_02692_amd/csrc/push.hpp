@@ -61,6 +61,7 @@ Slp push_as_slp(const PushDag &d);
 struct PushOpts {
   int slots = 40;     // register slots (16 B per lane each)
   int max_ring = 12;  // most input strips loaded ahead of their use
+  int prefetch = 0;   // strips touched this far ahead of their register load (0 = none)
 };
 
 struct PushCode {
@@ -71,6 +72,7 @@ struct PushCode {
   int passes = 0;     // passes over the inputs (more than one only when the rows do not fit)
   int n_loads = 0;
   int n_stores = 0;
+  int n_prefetch = 0;
   int n_records = 0;
   int n_ops = 0;      // run operands (slot XORs) per tile
 };

@@ -11,7 +11,7 @@ previous one left, and every tile must store the same values and leave
 every slot zero (the next tile may run another program).
 """
 
-KINDS = {0: "RUN", 1: "INPUT", 2: "INPUT_LD", 3: "VALUE", 4: "STORE", 5: "LOAD", 6: "HALT"}
+KINDS = {0: "RUN", 1: "INPUT", 2: "INPUT_LD", 3: "VALUE", 4: "STORE", 5: "LOAD", 6: "HALT", 7: "PREFETCH"}
 
 
 class SimError(AssertionError):
@@ -66,7 +66,8 @@ def simulate(words, slots, n_in_blocks, n_out_blocks, tiles=2):
             check(waits or f["wait8"] == 0, "stray wait at %d" % pc)
             check(f["wait8"] % 8 == 0 and f["ld16"] % 16 == 0, "scaled fields at %d" % pc)
             check(loads or f["ld16"] == 0, "stray load slot at %d" % pc)
-            check(loads or kind == "STORE" or (f["blk"] == 0 and f["j"] == 0), "stray strip at %d" % pc)
+            check(loads or kind in ("STORE", "PREFETCH") or (f["blk"] == 0 and f["j"] == 0),
+                  "stray strip at %d" % pc)
             if waits:
                 keep = f["wait8"] // 8
                 while len(vm) > keep:
@@ -84,6 +85,9 @@ def simulate(words, slots, n_in_blocks, n_out_blocks, tiles=2):
                 val[s] = 1 << (8 * f["blk"] + f["j"])
                 busy[s] = True
                 vm.append(s)
+            if kind == "PREFETCH":
+                check(f["blk"] < n_in_blocks and n == 0, "prefetch fields at %d" % pc)
+                vm.append(None)
             if kind == "STORE":
                 check(n_in_blocks <= f["blk"] < n_in_blocks + n_out_blocks, "store block at %d" % pc)
                 o = 8 * (f["blk"] - n_in_blocks) + f["j"]

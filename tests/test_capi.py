@@ -108,7 +108,7 @@ def test_interpreter_layout(built):
         for h, W in ((base[84], 36), (base[86], 52)):
             assert h % 512 == 0
             for kind in range(8):
-                want = "s_branch" if kind >= 6 else "s_bfe_u32 s74, s%d, 0x7000c" % W
+                want = "s_branch" if kind == 6 else "s_bfe_u32 s74, s%d, 0x7000c" % W
                 assert ins.get(h + 512 * kind, "").startswith(want), (name, kind)
         for r, W in ((base[88], 36), (base[90], 52)):
             for step in range(14):
@@ -118,3 +118,6 @@ def test_interpreter_layout(built):
             assert ins.get(base[92] + 16 * k, "").startswith("global_load_dwordx4 v[%d:%d]" % (4 + 4 * k, 7 + 4 * k))
         for k in range(64):
             assert ins.get(base[94] + 8 * k, "").startswith("s_waitcnt vmcnt(%d)" % k)
+        # the prefetch handler writes only the pinned scratch register
+        pf = [ins[a] for a in addrs if base[84] + 7 * 512 <= a < base[84] + 8 * 512 and "global_load" in ins[a]]
+        assert pf == ["global_load_dword v%d, v%s, s[72:73]" % (4 + 4 * K, pf[0].split(", v")[1].split(",")[0])]

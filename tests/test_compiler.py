@@ -179,6 +179,16 @@ def test_block_width_option_keeps_semantics(width):
     assert [got[o] for o in range(32)] == rows
 
 
+@pytest.mark.parametrize("dist", [1, 4, 12, 64])
+def test_prefetch_distance_keeps_semantics(dist):
+    gen = E.ec_matrix_cauchy(10, 4)
+    for er, level in (((), E.LEVEL_PLAIN), ((), E.LEVEL_CO_FU_SCHED), ((1, 7, 12), E.LEVEL_CO_FU_SCHED)):
+        rows = oracle_rows(gen, 10, 4, er)
+        prog = E.ec_compile_slp(10, 4, gen, er, level=level, prefetch=dist)
+        got = simulate(prog.bytecode(), prog.info["slots"], 10, len(prog.out_blocks))
+        assert [got[o] for o in range(len(rows))] == rows
+
+
 def test_compressed_beats_plain_in_xors():
     gen = E.ec_matrix_cauchy(10, 4)
     plain = E.ec_compile_slp(10, 4, gen, level=E.LEVEL_PLAIN)
