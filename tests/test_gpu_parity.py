@@ -117,6 +117,20 @@ def test_encode_row_passes_and_block_widths():
         assert_blocks_equal(run_encode(prog, data, 1 << 20), want, "width %d" % width)
 
 
+@pytest.mark.parametrize("dist", [4, 12, 20])
+def test_encode_decode_with_prefetch(dist):
+    n, p, S = 10, 4, (1 << 20) + 640
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=dist)
+    blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
+    for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+        prog = E.ec_compile_slp(n, p, gen, level=level, prefetch=dist)
+        assert_blocks_equal(run_encode(prog, data, S), blocks[n:], "encode level %d prefetch %d" % (level, dist))
+        er = (1, 5, 10, 12)
+        prog = E.ec_compile_slp(n, p, gen, er, level=level, prefetch=dist)
+        assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], "decode prefetch %d" % dist)
+
+
 def all_patterns(n, p):
     return [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
 
