@@ -16,6 +16,10 @@ struct ExecArgs {
   uint32_t n_in;             // input blocks
   uint32_t n_tiles;          // ceil(strip_len / kTileBytes)
   uint64_t strip_len;        // bytes per strip (block_bytes / 8), multiple of 16
+  // Work item k runs tile (k & seg_mask) * seg_tiles + (k >> seg_shift):
+  // consecutive waves take tiles in 1 << seg_shift distant segments of the
+  // strips (identity when seg_shift = 0).
+  uint32_t seg_shift, seg_mask, seg_tiles;
 };
 
 // One stripe of a batched launch (device memory, read-only during a launch).

@@ -231,7 +231,8 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
   const uint32_t *prog = a.prog;
   %(DECLS)s
   EC_INIT_%(K)d;
-  for (uint32_t tile = wave; tile < a.n_tiles; tile += n_waves) {
+  for (uint32_t k = wave; k < a.n_tiles; k += n_waves) {
+    const uint32_t tile = (k & a.seg_mask) * a.seg_tiles + (k >> a.seg_shift);
     const uint64_t toff = (uint64_t)tile * kTileBytes;
     const uint64_t t = tile_table(tab, toff);
     const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
