@@ -116,6 +116,7 @@ def test_interpreter_layout(built):
             assert ins.get(r + 280) == "s_set_gpr_idx_off"
         for k in range(K):
             assert ins.get(base[92] + 16 * k, "").startswith("global_load_dwordx4 v[%d:%d]" % (4 + 4 * k, 7 + 4 * k))
+            assert ins[base[92] + 16 * k].endswith(" nt")
         for k in range(64):
             assert ins.get(base[94] + 8 * k, "").startswith("s_waitcnt vmcnt(%d)" % k)
         # the prefetch handler writes only the pinned scratch register
