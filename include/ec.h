@@ -148,6 +148,12 @@ ec_status ec_encode(const ec_program *prog, const uint8_t *const *data, uint8_t 
 ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uint8_t *const *recovered,
                     size_t block_bytes, ec_stream stream);
 
+/* Copy the program's records to the current device now (synchronously, one
+ * small allocation per device and program).  Otherwise the first launch on
+ * a device does it, which a latency-sensitive caller may not want.
+ * Errors: EC_ERR_ARG, EC_ERR_NOMEM, EC_ERR_DEVICE. */
+ec_status ec_program_upload(ec_program *prog);
+
 void ec_program_free(ec_program *prog);
 const char *ec_status_str(ec_status s);
 
@@ -222,6 +228,12 @@ ec_status ec_batch_enqueue(ec_batch *batch, ec_stream stream);
 ec_status ec_batch_create(ec_batch **out);
 ec_status ec_batch_set(ec_batch *batch, const ec_stripe *stripes, int n_stripes, size_t tile_bytes,
                        ec_stream stream);
+
+/* Size the batch's tables now for up to n_stripes stripes and n_items work
+ * items, so that later ec_batch_set calls up to those sizes allocate
+ * nothing (allocation and release can synchronise the device).
+ * Errors: EC_ERR_ARG, EC_ERR_DEVICE (other current device), EC_ERR_NOMEM. */
+ec_status ec_batch_reserve(ec_batch *batch, int n_stripes, size_t n_items);
 
 /* Number of work items and total input/output bytes of a batch. */
 ec_status ec_batch_query(const ec_batch *batch, size_t *n_items, size_t *in_bytes, size_t *out_bytes);

@@ -89,6 +89,8 @@ def lib():
         L.ec_program_bytecode.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
                                           ctypes.POINTER(ctypes.c_size_t)]
         L.ec_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.ec_program_upload.argtypes = [vp]
+        L.ec_batch_reserve.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
         L.ec_batch_build.argtypes = [ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.ec_batch_launch.argtypes = [vp, vp]
         L.ec_batch_enqueue.argtypes = [vp, vp]
@@ -211,6 +213,11 @@ class Program:
             i += 2 + ar
         return stmts, v[i:i + no]
 
+    def upload(self):
+        """Copy the records to the current device now (else the first launch
+        does it, synchronously)."""
+        _check(lib().ec_program_upload(self._h), "ec_program_upload")
+
     def bytecode(self):
         w = ctypes.POINTER(ctypes.c_uint32)()
         n = ctypes.c_size_t()
@@ -278,6 +285,10 @@ class Batch:
                "ec_batch_set")
         self._keep = keep
         self._query()
+
+    def reserve(self, n_stripes: int, n_items: int):
+        """Size the tables so that ``set`` up to these sizes allocates nothing."""
+        _check(lib().ec_batch_reserve(self._h, n_stripes, n_items), "ec_batch_reserve")
 
     def launch(self, stream=None):
         """One launch of the batch's HIP graph (reset + persistent kernel)."""

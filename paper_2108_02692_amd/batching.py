@@ -74,6 +74,13 @@ class ProgramCache:
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(lambda k: self.get(*k), keys))
 
+    def upload(self):
+        """Copy every cached program's records to the current device."""
+        with self._lock:
+            progs = list(self._progs.values())
+        for prog in progs:
+            prog.upload()
+
     def all_patterns(self, n, p):
         return [()] + [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
 

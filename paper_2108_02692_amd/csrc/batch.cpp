@@ -20,6 +20,7 @@ using namespace ec;
 
 struct ec_batch {
   int device = 0;
+  int n_cus = 0;  // compute units of the device (read once: the query is slow)
   int slots = 0;
   int grid = 0;
   size_t n_items = 0, in_bytes = 0, out_bytes = 0;
@@ -55,6 +56,40 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 // 4 + 4K + a few of the kernel's own, allocated in granules of 8, out of 512.
 int waves_per_simd(int slots) { return slots <= 24 ? 4 : slots <= 38 ? 3 : 2; }
 
+// Grows the device tables and their pinned staging to hold n_desc stripes
+// and n_words item words (never shrinks).
+ec_status grow(ec_batch *b, size_t n_desc, size_t n_words) {
+  if (n_desc > b->cap_desc) {
+    const size_t cap = std::max(n_desc, 2 * b->cap_desc);
+    StripeDesc *d = nullptr, *h = nullptr;
+    if (hipMalloc((void **)&d, cap * sizeof(StripeDesc)) != hipSuccess) return EC_ERR_NOMEM;
+    if (hipHostMalloc((void **)&h, cap * sizeof(StripeDesc), hipHostMallocDefault) != hipSuccess) {
+      (void)hipFree(d);
+      return EC_ERR_NOMEM;
+    }
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    b->d_desc = d;
+    b->h_desc = h;
+    b->cap_desc = cap;
+  }
+  if (n_words > b->cap_items) {
+    const size_t cap = std::max(n_words, 2 * b->cap_items);
+    uint32_t *d = nullptr, *h = nullptr;
+    if (hipMalloc((void **)&d, cap * sizeof(uint32_t)) != hipSuccess) return EC_ERR_NOMEM;
+    if (hipHostMalloc((void **)&h, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      (void)hipFree(d);
+      return EC_ERR_NOMEM;
+    }
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->h_items) (void)hipHostFree(b->h_items);
+    b->d_items = d;
+    b->h_items = h;
+    b->cap_items = cap;
+  }
+  return EC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -65,6 +100,8 @@ ec_status ec_batch_create(ec_batch **out) {
   std::unique_ptr<ec_batch> b(new (std::nothrow) ec_batch);
   if (!b) return EC_ERR_NOMEM;
   if (hipGetDevice(&b->device) != hipSuccess) return EC_ERR_DEVICE;
+  if (hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
+    return EC_ERR_DEVICE;
   if (hipMalloc((void **)&b->d_counter, 256) != hipSuccess) return EC_ERR_NOMEM;
   *out = b.release();
   return EC_OK;
@@ -120,35 +157,8 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     out_bytes += (size_t)n_out * st.block_bytes;
   }
   if (items.size() / 2 > 0xFFFFFFFFull) return EC_ERR_UNSUPPORTED;
-  // grow device tables and pinned staging when needed
-  if (desc.size() > b->cap_desc) {
-    const size_t cap = std::max(desc.size(), 2 * b->cap_desc);
-    StripeDesc *d = nullptr, *h = nullptr;
-    if (hipMalloc((void **)&d, cap * sizeof(StripeDesc)) != hipSuccess) return EC_ERR_NOMEM;
-    if (hipHostMalloc((void **)&h, cap * sizeof(StripeDesc), hipHostMallocDefault) != hipSuccess) {
-      (void)hipFree(d);
-      return EC_ERR_NOMEM;
-    }
-    if (b->d_desc) (void)hipFree(b->d_desc);
-    if (b->h_desc) (void)hipHostFree(b->h_desc);
-    b->d_desc = d;
-    b->h_desc = h;
-    b->cap_desc = cap;
-  }
-  if (items.size() > b->cap_items) {
-    const size_t cap = std::max(items.size(), 2 * b->cap_items);
-    uint32_t *d = nullptr, *h = nullptr;
-    if (hipMalloc((void **)&d, cap * sizeof(uint32_t)) != hipSuccess) return EC_ERR_NOMEM;
-    if (hipHostMalloc((void **)&h, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
-      (void)hipFree(d);
-      return EC_ERR_NOMEM;
-    }
-    if (b->d_items) (void)hipFree(b->d_items);
-    if (b->h_items) (void)hipHostFree(b->h_items);
-    b->d_items = d;
-    b->h_items = h;
-    b->cap_items = cap;
-  }
+  ec_status gs = grow(b, desc.size(), items.size());
+  if (gs != EC_OK) return gs;
   std::copy(desc.begin(), desc.end(), b->h_desc);
   std::copy(items.begin(), items.end(), b->h_items);
   const hipStream_t hs = (hipStream_t)stream;
@@ -166,13 +176,18 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   b->args.n_items = (uint32_t)b->n_items;
   b->args.counter = b->d_counter;
   b->args.tiles_per_item = tiles_per_item;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return EC_ERR_DEVICE;
-  b->grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)prop.multiProcessorCount * waves_per_simd(b->slots),
+  b->grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)b->n_cus * waves_per_simd(b->slots),
                                                       (b->n_items + 3) / 4));
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return EC_OK;
+}
+
+ec_status ec_batch_reserve(ec_batch *b, int n_stripes, size_t n_items) {
+  if (!b || n_stripes < 0) return EC_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return EC_ERR_DEVICE;
+  return grow(b, (size_t)n_stripes, 2 * n_items);
 }
 
 ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,

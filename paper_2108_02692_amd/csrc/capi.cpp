@@ -317,6 +317,12 @@ ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream str
   return copy_launch(src, dst, bytes, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
 }
 
+ec_status ec_program_upload(ec_program *prog) {
+  if (!prog) return EC_ERR_ARG;
+  ec_status st = EC_OK;
+  return prog->device_words(&st) ? EC_OK : st;
+}
+
 ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, size_t *n_words) {
   if (!prog || !words || !n_words) return EC_ERR_ARG;
   *words = prog->code.words.data();

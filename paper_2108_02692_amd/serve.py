@@ -18,6 +18,7 @@ ceil(b / n) bytes rounded up to 512.
 from __future__ import annotations
 
 import bisect
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -25,6 +26,8 @@ import numpy as np
 
 from . import LEVEL_CO_FU_SCHED, Batch
 from .batching import ProgramCache
+
+MAX_OBJECT = 64 << 20  # largest object served (bytes)
 
 
 @dataclass
@@ -97,12 +100,19 @@ class Server:
         self.cache = ProgramCache(level=level, slots=slots)
         if warm:
             self.cache.warm([(n, p, er) for n, p in codecs for er in self.cache.all_patterns(n, p)])
+            # every program resident on the device before the clock starts
+            self.cache.upload()
         self.arena = torch.empty(budget_bytes, dtype=torch.uint8, device="cuda")
         self.base = self.arena.data_ptr()
         self.heap = FirstFit(budget_bytes)
         self.slots = []
+        # Work items per request: one per tile of a strip; the largest object
+        # (64 MiB) over the fewest data blocks of the served codecs.
+        max_items = max_batch * (-(-(MAX_OBJECT // min(n for n, _ in codecs)) // 8 // 1024) + 1)
         for _ in range(n_slots):
-            self.slots.append({"stream": torch.cuda.Stream(), "batch": Batch.create(), "event": None,
+            b = Batch.create()
+            b.reserve(max_batch, max_items)  # no allocation while serving
+            self.slots.append({"stream": torch.cuda.Stream(), "batch": b, "event": torch.cuda.Event(),
                                "reqs": None})
         self.batches = 0
 
@@ -129,9 +139,7 @@ class Server:
         stripes = [(self.cache.get(r.n, r.p, r.erased), r.inputs, r.outputs, r.block_bytes) for r in reqs]
         slot["batch"].set(stripes, tile_bytes=self.tile_bytes, stream=slot["stream"])
         slot["batch"].enqueue(slot["stream"])
-        ev = self.torch.cuda.Event()
-        ev.record(slot["stream"])
-        slot["event"] = ev
+        slot["event"].record(slot["stream"])
         slot["reqs"] = reqs
         self.batches += 1
 
@@ -182,7 +190,7 @@ class Server:
 
 
 def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool_bytes: int,
-                  ratio_10_4=0.75, encode_frac=0.7, median=256 << 10, sigma=1.0, lo=4 << 10, hi=64 << 20):
+                  ratio_10_4=0.75, encode_frac=0.7, median=256 << 10, sigma=1.0, lo=4 << 10, hi=MAX_OBJECT):
     """Seeded Poisson arrivals over ``duration_s``; inputs point into a
     read-only device pool."""
     import itertools
@@ -218,7 +226,14 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     setup_s = time.perf_counter() - t_setup
     reqs = make_requests(duration_s, rate, seed, pool.data_ptr(), pool_bytes)
     torch.cuda.synchronize()
-    wall = server.serve(reqs)
+    # no collector pauses inside the timed loop (the request objects are
+    # all allocated beforehand)
+    gc.collect()
+    gc.disable()
+    try:
+        wall = server.serve(reqs)
+    finally:
+        gc.enable()
     torch.cuda.synchronize()
     lat = np.array([r.done - r.arrival for r in reqs])
     in_bytes = sum(r.n * r.block_bytes for r in reqs)

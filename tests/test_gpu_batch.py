@@ -73,3 +73,27 @@ def test_batch_rejects_mixed_slot_budgets():
     with pytest.raises(E.EcError) as e:
         E.ec_batch_build([(a, d, o1, 4096), (b, d, o2, 4096)])
     assert e.value.name == "EC_ERR_UNSUPPORTED"
+
+
+def test_reusable_batch_reserve_and_refill():
+    """create + reserve + set/enqueue twice with different stripes (the
+    serving pattern), programs uploaded beforehand; both runs match the
+    oracle."""
+    cache = B.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=38)
+    stream = torch.cuda.current_stream()
+    batch = E.Batch.create()
+    batch.reserve(64, 4096)
+    for seed in (11, 12):
+        specs = B.mixed_specs(40, seed=seed, codecs=((10, 4), (6, 3)), lo=4096, hi=32 * 1024)
+        for s in specs:
+            cache.get(s.n, s.p, s.erased)
+        cache.upload()
+        ins_h, want = make_case(specs, cache, seed=seed + 100)
+        ins = [W.to_device(x) for x in ins_h]
+        outs = [W.empty_blocks(s.n_out, s.block_bytes, fill=0xA5) for s in specs]
+        batch.set([(cache.get(s.n, s.p, s.erased), ins[k], outs[k], s.block_bytes) for k, s in enumerate(specs)],
+                  stream=stream)
+        batch.enqueue(stream)
+        torch.cuda.synchronize()
+        check(outs, want, "refill seed %d" % seed)
+    batch.free()
