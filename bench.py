@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
-    ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy"], default="all",
+    ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve"],
+                    default="all",
                     help="time one kernel only (for profiler runs)")
     ap.add_argument("--calib", action="store_true",
                     help="also run one device copy of 448 MiB (byte-counter calibration)")
@@ -118,10 +119,17 @@ def main():
         print("bench.py: no ROCm GPU visible", file=sys.stderr)
         sys.exit(1)
     E.lib()  # fails loudly if the HIP library is missing
+    stream = torch.cuda.current_stream()
+    if args.only == "batched":
+        print(json.dumps({"batched": bench_batched(args, stream)}), flush=True)
+        return
+    if args.only == "serve":
+        from paper_2108_02692_amd import serve
+        print(json.dumps({"serving": serve.run(duration_s=args.serve_seconds, seed=7)}), flush=True)
+        return
     n, p = 10, 4
     S = args.block_mib << 20
     gen = E.ec_matrix_cauchy(n, p)
-    stream = torch.cuda.current_stream()
     data = W.device_blocks(n, S, seed=2021)
     parity = W.empty_blocks(p, S)
     torch.cuda.synchronize()
