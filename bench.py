@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--sweep", action="store_true",
                     help="time every (level, slot budget) pair on the workload and print one line each")
+    ap.add_argument("--sweep-prefetch", action="store_true", help="with --sweep: also vary the prefetch distance")
     return ap.parse_args()
 
 
@@ -150,7 +151,7 @@ def main():
     if args.sweep:
         for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
             for K in (32, 36, 38, 40, 44, 48):
-                for dist in (0, 4, 8, 12, 20):
+                for dist in ((0, 4, 12) if args.sweep_prefetch else (0,)):
                     pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K, prefetch=dist)
                     ms = measure(pr, data, parity)
                     print(json.dumps({"sweep": True, "level": level, "slots": K, "prefetch": dist, "ms": ms,
