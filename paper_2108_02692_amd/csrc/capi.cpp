@@ -155,11 +155,11 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   const std::vector<Bits> brows = bitmatrix_rows(n_out, n, rows);
   const int n_const = 8 * n;
 
-  // The paper's whole-matrix pipeline (Secs. 2-6), kept for inspection.
+  // The paper's whole-matrix pipeline (Secs. 2-6) is built on first export
+  // only (it is for inspection; the executed program is built below).
   prog->plain = plain_slp(brows, n_const);
-  if (o.level >= EC_LEVEL_CO) prog->co = xor_repair(brows, n_const, o.compress == EC_COMPRESS_XORREPAIR);
-  if (o.level >= EC_LEVEL_CO_FU) prog->fu = fuse(prog->co);
-  if (o.level >= EC_LEVEL_CO_FU_SCHED) prog->sched = dfs_schedule(prog->fu);
+  prog->brows = brows;
+  prog->rebuild = o.compress == EC_COMPRESS_XORREPAIR;
 
   // The executed program, in push form.
   const int width = o.block_strips ? (int)o.block_strips : 8;
@@ -293,6 +293,7 @@ const char *ec_status_str(ec_status s) {
 ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, size_t cap, size_t *len) {
   if (!prog || !len) return EC_ERR_ARG;
   const Slp *s = nullptr;
+  if (stage >= EC_STAGE_CO && stage <= EC_STAGE_SCHED) const_cast<ec_program *>(prog)->paper_stages();
   switch (stage) {
     case EC_STAGE_PLAIN: s = &prog->plain; break;
     case EC_STAGE_CO: s = prog->level >= EC_LEVEL_CO ? &prog->co : nullptr; break;

@@ -20,6 +20,9 @@ struct ec_program {
   int slots = 32;
   std::vector<int> in_blocks, out_blocks;
   ec::Slp plain, co, fu, sched;  // the paper's whole-matrix stages (co/fu/sched per level)
+  std::vector<ec::Bits> brows;   // the bitmatrix rows (input of the stages)
+  bool rebuild = true;           // XorRePair (else RePair)
+  bool stages_built = false;
   ec::Slp exec;                  // the push-form program the executor runs, as an SLP
   ec::PushCode code;
   ec_program_info info{};
@@ -34,6 +37,17 @@ struct ec_program {
         (void)hipSetDevice(cur);
       }
     }
+  }
+
+  // Builds the whole-matrix CO/FU/SCHED stages of the program's level once.
+  void paper_stages() {
+    std::lock_guard<std::mutex> g(mu);
+    if (stages_built) return;
+    const int n_const = plain.n_const;
+    if (level >= EC_LEVEL_CO) co = ec::xor_repair(brows, n_const, rebuild);
+    if (level >= EC_LEVEL_CO_FU) fu = ec::fuse(co);
+    if (level >= EC_LEVEL_CO_FU_SCHED) sched = ec::dfs_schedule(fu);
+    stages_built = true;
   }
 
   // Device copy of the bytecode for the current device (uploaded once).
