@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
-    ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve"],
+    ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve",
+                                       "decode_all"],
                     default="all",
                     help="time one kernel only (for profiler runs)")
     ap.add_argument("--calib", action="store_true",
@@ -123,6 +124,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.only == "batched":
         print(json.dumps({"batched": bench_batched(args, stream)}), flush=True)
+        return
+    if args.only == "decode_all":
+        print(json.dumps({"decode_all": bench_decode_all(args, stream)}), flush=True)
         return
     if args.only == "serve":
         from paper_2108_02692_amd import serve
@@ -249,9 +253,14 @@ def main():
     out.update(extra)
     if "copy_ceiling_GB_s" in out:
         out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GB_s"]
-    if args.only == "all" and args.batch_stripes > 0:
+    if args.only == "all":
         del data, parity
         torch.cuda.empty_cache()
+        log("decode of every erasure set ...")
+        out["decode_all"] = bench_decode_all(args, stream)
+        log("decode all: %.3f ms" % out["decode_all"]["ms"])
+        torch.cuda.empty_cache()
+    if args.only == "all" and args.batch_stripes > 0:
         log("batched ...")
         out["batched"] = bench_batched(args, stream)
         log("batched: %.3f ms" % out["batched"]["ms"])
@@ -308,6 +317,52 @@ def bench_batched(args, stream):
         res["autotune"] = table
     batch.free()
     del pool, out_buf, inputs, outputs
+    return res
+
+
+def bench_decode_all(args, stream):
+    """RS(10,4) decode of every erasure set of at most 4 blocks (1470 sets,
+    1001 of them with 4 blocks lost): each set has its own 10 data blocks of
+    1 MiB of seeded random bytes, encoded on the device; one batched launch
+    reconstructs every erased block of every set, and every result is
+    compared with the block it replaces."""
+    import itertools
+    import torch
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import batching
+
+    n, p, S = 10, 4, 1 << 20
+    pats = [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
+    P = len(pats)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    data = torch.randint(0, 256, (P, n, S), dtype=torch.uint8, device="cuda", generator=g)
+    parity = torch.empty((P, p, S), dtype=torch.uint8, device="cuda")
+    cache = batching.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=38)
+    enc = cache.get(n, p)
+    encode = E.ec_batch_build([(enc, list(data[k]), list(parity[k]), S) for k in range(P)], stream=stream)
+    encode.launch(stream)
+    cache.warm([(n, p, er) for er in pats])
+    n_out = sum(len(er) for er in pats)
+    out = torch.empty((n_out, S), dtype=torch.uint8, device="cuda")
+    stripes, want, o = [], [], 0
+    for k, er in enumerate(pats):
+        prog = cache.get(n, p, er)
+        blocks = list(data[k]) + list(parity[k])
+        stripes.append((prog, [blocks[i] for i in prog.in_blocks], list(out[o:o + len(er)]), S))
+        want += [blocks[e] for e in er]
+        o += len(er)
+    batch = E.ec_batch_build(stripes, stream=stream)
+    ms = time_launches(lambda: batch.launch(stream), max(3, args.steps // 2), 1, stream)
+    ok = all(torch.equal(out[j], want[j]) for j in range(n_out))
+    if not ok:
+        raise SystemExit("bench.py: decode-all self-check failed")
+    in_bytes = P * n * S
+    res = {"patterns": P, "block_bytes": S, "ms": ms, "GB_s": in_bytes / ms / 1e6,
+           "hbm_frac": (in_bytes + n_out * S) / ms / 1e6 / HBM_PEAK_GBS, "slots": 38, "verified": ok}
+    encode.free()
+    batch.free()
+    del data, parity, out
     return res
 
 
