@@ -122,3 +122,50 @@ def test_interpreter_layout(built):
         # the prefetch handler writes only the pinned scratch register
         pf = [ins[a] for a in addrs if base[84] + 7 * 512 <= a < base[84] + 8 * 512 and "global_load" in ins[a]]
         assert pf == ["global_load_dword v%d, v%s, s[72:73]" % (4 + 4 * K, pf[0].split(", v")[1].split(",")[0])]
+
+
+def test_launch_argument_errors_need_no_device():
+    """Every argument check of ec_encode / ec_decode happens before any HIP
+    call, so it is reported on a host without a GPU too (pointers here are
+    plain integers, never dereferenced)."""
+    gen = E.ec_matrix_cauchy(10, 4)
+    enc = E.ec_compile_slp(10, 4, gen)
+    dec = E.ec_compile_slp(10, 4, gen, [3])
+    S = 1 << 16
+    ins = [0x100000 + k * S for k in range(10)]
+    outs = [0x10000000 + k * S for k in range(4)]
+    cases = [
+        (lambda: E.ec_encode(enc, ins, outs, 0), "EC_ERR_ALIGN"),
+        (lambda: E.ec_encode(enc, ins, outs, S + 64), "EC_ERR_ALIGN"),
+        (lambda: E.ec_encode(enc, ins[:-1] + [ins[-1] + 8], outs, S), "EC_ERR_ALIGN"),
+        (lambda: E.ec_encode(enc, ins, outs[:-1] + [ins[0] + 128], S), "EC_ERR_ARG"),  # output overlaps an input
+        (lambda: E.ec_encode(enc, ins, outs[:-1] + [outs[0] + 128], S), "EC_ERR_ARG"),  # outputs overlap
+        (lambda: E.ec_encode(enc, ins[:-1] + [0], outs, S), "EC_ERR_ARG"),
+        (lambda: E.ec_encode(enc, ins, outs, 8 << 29), "EC_ERR_UNSUPPORTED"),  # strips of 512 MiB: too long
+        (lambda: E.ec_decode(enc, ins, outs, S), "EC_ERR_ARG"),
+        (lambda: E.ec_encode(dec, ins, outs[:1], S), "EC_ERR_ARG"),
+    ]
+    for call, name in cases:
+        with pytest.raises(E.EcError) as e:
+            call()
+        assert e.value.name == name
+
+
+def test_compile_limits_and_degenerate_codecs():
+    from bytecode_sim import simulate
+    import numpy as np
+    import oracle
+    from oracle import slp as S
+    for n, p, er in ((1, 1, ()), (1, 3, ()), (1, 3, (0,)), (1, 3, (0, 2, 3)), (2, 0, ()), (28, 4, ()),
+                     (28, 4, (0, 5, 27, 31)), (31, 1, (30,)), (4, 12, ())):
+        gen = E.ec_matrix_cauchy(n, p)
+        G = np.array(gen, dtype=np.uint8)
+        D = oracle.decode_matrix(G, n, p, list(er))[0] if er else G[n:]
+        rows = S.rows_from_bitmatrix(oracle.bitmatrix(D)) if len(D) else []
+        for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+            prog = E.ec_compile_slp(n, p, gen, list(er), level=level)
+            got = simulate(prog.bytecode(), prog.info["slots"], n, len(prog.out_blocks))
+            assert [got[o] for o in range(len(rows))] == rows, (n, p, er, level)
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(29, 4, E.ec_matrix_cauchy(29, 4))  # 33 blocks > the 32-entry table
+    assert e.value.name == "EC_ERR_ARG"

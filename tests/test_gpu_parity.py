@@ -131,6 +131,24 @@ def test_encode_decode_with_prefetch(dist):
         assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], "decode prefetch %d" % dist)
 
 
+@pytest.mark.parametrize("n,p,er", [(1, 3, ()), (1, 3, (0, 2)), (28, 4, ()), (28, 4, (1, 9, 27, 30)),
+                                    (4, 12, ()), (4, 12, (0, 3, 5, 15)), (2, 0, ())])
+def test_degenerate_and_wide_codecs(n, p, er):
+    """Replication (n = 1), the widest stripe (32 blocks), more rows than
+    slots (RS(4,12): several passes over the inputs) and no parity at all."""
+    S = 8192 + 128
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.host_blocks(n, S, seed=n * 100 + p)
+    blocks = data + (oracle.encode(np.array(gen, dtype=np.uint8), n, p, data) if p else [])
+    for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+        prog = E.ec_compile_slp(n, p, gen, list(er), level=level)
+        if er:
+            got = run_decode(prog, blocks, S)
+            assert_blocks_equal(got, [blocks[e] for e in er], "RS(%d,%d) decode %s" % (n, p, er))
+        else:
+            assert_blocks_equal(run_encode(prog, data, S), blocks[n:], "RS(%d,%d) encode" % (n, p))
+
+
 def all_patterns(n, p):
     return [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
 
