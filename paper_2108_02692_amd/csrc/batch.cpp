@@ -1,10 +1,9 @@
 // batch.cpp -- many stripes in one persistent launch.
 //
 // A batch is a table of stripe descriptors and a list of work items
-// (stripe, first tile), uploaded once.  A launch resets the work counter with
-// a one-thread kernel and starts the persistent executor, whose waves pull
-// items until the list is exhausted; both launches are captured into a HIP
-// graph at build time, so a launch is one graph launch.
+// (stripe, first tile), uploaded once.  A launch is the persistent executor,
+// whose wave w runs items w, w + W, ... of the list (W waves); it is
+// captured into a HIP graph at build time, so a launch is one graph launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +28,6 @@ struct ec_batch {
   StripeDesc *d_desc = nullptr, *h_desc = nullptr;
   uint32_t *d_items = nullptr, *h_items = nullptr;
   size_t cap_desc = 0, cap_items = 0;
-  uint32_t *d_counter = nullptr;
   BatchArgs args{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -41,7 +39,6 @@ struct ec_batch {
     if (graph) (void)hipGraphDestroy(graph);
     if (d_desc) (void)hipFree(d_desc);
     if (d_items) (void)hipFree(d_items);
-    if (d_counter) (void)hipFree(d_counter);
     if (h_desc) (void)hipHostFree(h_desc);
     if (h_items) (void)hipHostFree(h_items);
     if (swap) (void)hipSetDevice(cur);
@@ -102,7 +99,6 @@ ec_status ec_batch_create(ec_batch **out) {
   if (hipGetDevice(&b->device) != hipSuccess) return EC_ERR_DEVICE;
   if (hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
     return EC_ERR_DEVICE;
-  if (hipMalloc((void **)&b->d_counter, 256) != hipSuccess) return EC_ERR_NOMEM;
   *out = b.release();
   return EC_OK;
 }
@@ -146,7 +142,7 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     ec_status ws = EC_OK;
     d.prog = const_cast<ec_program *>(prog)->device_words(&ws);
     if (!d.prog) return ws;
-    d.n_in = (uint32_t)n_in;
+    d.n_blocks = (uint32_t)(n_in + n_out);
     d.strip_len = (uint32_t)(st.block_bytes / 8);
     const uint32_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
     for (uint32_t t = 0; t < n_tiles; t += tiles_per_item) {
@@ -174,7 +170,6 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   b->args.stripes = b->d_desc;
   b->args.items = b->d_items;
   b->args.n_items = (uint32_t)b->n_items;
-  b->args.counter = b->d_counter;
   b->args.tiles_per_item = tiles_per_item;
   b->grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)b->n_cus * waves_per_simd(b->slots),
                                                       (b->n_items + 3) / 4));
@@ -201,7 +196,7 @@ ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_by
   st = ec_batch_set(b.get(), stripes, n_stripes, tile_bytes, stream);
   if (st != EC_OK) return st;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return EC_ERR_DEVICE;
-  // Capture reset + persistent kernel into a graph on a private stream.
+  // Capture the persistent kernel into a graph on a private stream.
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return EC_ERR_DEVICE;
   bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) == hipSuccess;

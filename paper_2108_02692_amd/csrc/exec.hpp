@@ -26,7 +26,7 @@ struct ExecArgs {
 struct StripeDesc {
   uint64_t blk[kMaxBlocks];  // input block pointers, then output block pointers
   const uint32_t *prog;      // the stripe's device bytecode
-  uint32_t n_in;             // input blocks
+  uint32_t n_blocks;         // input + output blocks
   uint32_t strip_len;        // bytes per strip
 };
 
@@ -36,10 +36,9 @@ struct BatchArgs {
   const uint32_t *items;  // 2 words per work item: stripe index, tile index
   uint32_t n_items;
   uint32_t tiles_per_item;  // consecutive tiles one work item covers
-  uint32_t *counter;        // next work item; reset to 0 by the launch itself
 };
 
-// Reset the work counter and launch the persistent kernel for `slots`.
+// Launch the persistent kernel for `slots` (wave w runs items w, w + W, ...).
 int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream);
 
 // Launch the executor instance for `slots` register slots; 0 on success.

@@ -84,7 +84,7 @@ def test_executor_isa(built):
         outside = re.sub(r";;#ASMSTART.*?;;#ASMEND", "", body, flags=re.S)
         assert not re.search(r"\bm0\b", outside), name
         vgprs = int(meta[name])
-        assert vgprs <= 4 + 4 * K + 12, (name, vgprs)
+        assert 4 + 4 * K + 1 <= vgprs <= 256, (name, vgprs)
         # the occupancy the batch launcher assumes (granules of 8 of 512)
         waves = 512 // (-(-vgprs // 8) * 8)
         assert waves >= (4 if K <= 24 else 3 if K <= 38 else 2), (name, vgprs)
