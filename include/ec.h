@@ -208,15 +208,15 @@ typedef struct {
 ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
                          ec_batch **out);
 
-/* Run the batch: one launch of the HIP graph built by ec_batch_build (the
- * persistent executor: wave w of W runs work items w, w + W, ..., an item
- * being `tile_bytes` of one stripe's strips).  Launches of one batch may be
- * queued back to back; they must not run concurrently on different streams
- * while ec_batch_set refills the batch. */
+/* Run the batch: one launch of the HIP graph built by ec_batch_build (a
+ * one-thread kernel resetting the work counter, then the persistent
+ * executor whose waves take chunks of (stripe, tile) work items from that
+ * counter).  Launches of one batch must not overlap (they share the
+ * counter). */
 ec_status ec_batch_launch(ec_batch *batch, ec_stream stream);
 
-/* The same kernel enqueued directly on `stream` instead of as a graph: for
- * callers that capture their own graphs (no allocation, no memset). */
+/* The same two kernels enqueued directly on `stream` instead of as a graph:
+ * for callers that capture their own graphs (no allocation, no memset). */
 ec_status ec_batch_enqueue(ec_batch *batch, ec_stream stream);
 
 /* A reusable batch for serving loops: ec_batch_create allocates an empty

@@ -1,9 +1,11 @@
 // batch.cpp -- many stripes in one persistent launch.
 //
 // A batch is a table of stripe descriptors and a list of work items
-// (stripe, first tile), uploaded once.  A launch is the persistent executor,
-// whose wave w runs items w, w + W, ... of the list (W waves); it is
-// captured into a HIP graph at build time, so a launch is one graph launch.
+// (stripe, first tile), uploaded once.  A launch resets the work counter with
+// a one-thread kernel and starts the persistent executor, whose waves take
+// chunks of items from the counter until the list is exhausted; both
+// launches are captured into a HIP graph at build time, so a launch is one
+// graph launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +29,7 @@ struct ec_batch {
   // shrunk (so refilling a batch in a serving loop allocates nothing)
   StripeDesc *d_desc = nullptr, *h_desc = nullptr;
   uint32_t *d_items = nullptr, *h_items = nullptr;
+  uint32_t *d_counter = nullptr;
   size_t cap_desc = 0, cap_items = 0;
   BatchArgs args{};
   hipGraph_t graph = nullptr;
@@ -39,6 +42,7 @@ struct ec_batch {
     if (graph) (void)hipGraphDestroy(graph);
     if (d_desc) (void)hipFree(d_desc);
     if (d_items) (void)hipFree(d_items);
+    if (d_counter) (void)hipFree(d_counter);
     if (h_desc) (void)hipHostFree(h_desc);
     if (h_items) (void)hipHostFree(h_items);
     if (swap) (void)hipSetDevice(cur);
@@ -99,6 +103,7 @@ ec_status ec_batch_create(ec_batch **out) {
   if (hipGetDevice(&b->device) != hipSuccess) return EC_ERR_DEVICE;
   if (hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
     return EC_ERR_DEVICE;
+  if (hipMalloc((void **)&b->d_counter, 256) != hipSuccess) return EC_ERR_NOMEM;
   *out = b.release();
   return EC_OK;
 }
@@ -173,6 +178,10 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   b->args.tiles_per_item = tiles_per_item;
   b->grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)b->n_cus * waves_per_simd(b->slots),
                                                       (b->n_items + 3) / 4));
+  // Items per atomic add: about an eighth of a wave's share, 1 to 16 (large
+  // chunks amortise the wait on the add, small ones keep the waves balanced).
+  b->args.chunk = (uint32_t)std::min<size_t>(16, std::max<size_t>(1, b->n_items / ((size_t)b->grid * 4 * 8)));
+  b->args.counter = b->d_counter;
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return EC_OK;

@@ -36,9 +36,11 @@ struct BatchArgs {
   const uint32_t *items;  // 2 words per work item: stripe index, tile index
   uint32_t n_items;
   uint32_t tiles_per_item;  // consecutive tiles one work item covers
+  uint32_t chunk;           // items taken per atomic add on the counter
+  uint32_t *counter;        // next work item; reset to 0 by the launch itself
 };
 
-// Launch the persistent kernel for `slots` (wave w runs items w, w + W, ...).
+// Reset the work counter and launch the persistent kernel for `slots`.
 int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream);
 
 // Launch the executor instance for `slots` register slots; 0 on success.

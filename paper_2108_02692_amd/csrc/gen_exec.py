@@ -243,46 +243,53 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
   }
 }
 
-// Wave w takes work items w, w + W, w + 2W, ... (W waves in the grid); an
+// Waves take work items from a device counter, `chunk` consecutive items
+// per atomic add (the add's result is a vector memory operation, so taking
+// it waits for the wave's earlier stores: chunks amortise that wait).  An
 // item covers tiles_per_item tiles of its stripe.  Items, descriptors and
-// block tables are read through the scalar cache, so no vector memory
-// operation (and no wait for the previous tile's stores) sits between two
-// tiles.  The host lists a stripe's tiles consecutively, so neighbouring
-// waves work on neighbouring tiles.
+// block tables are read through the scalar cache.  The host lists a
+// stripe's tiles consecutively.
 __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = blockIdx.x * 4u + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const uint32_t n_waves = gridDim.x * 4u;
   const uint32_t voff = lane * 16u;
   %(DECLS)s
   EC_INIT_%(K)d;
-  for (uint32_t it = wave; it < a.n_items; it += n_waves) {
-    const uint32_t stripe = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it];
-    const uint32_t tile = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it + 1];
-    ConstDescPtr d = (ConstDescPtr)(uintptr_t)(a.stripes + stripe);
-    const uint32_t *prog = d->prog;
-    const uint32_t sl = d->strip_len;
-    // lane b <- pointer of block b, from scalar loads (all 32 entries: the
-    // host zero-fills the unused ones)
-    uint64_t tab = 0;
+  for (;;) {
+    uint32_t first = 0;
+    if (lane == 0) first = atomicAdd(a.counter, a.chunk);
+    first = __builtin_amdgcn_readfirstlane(first);
+    if (first >= a.n_items) break;
+    const uint32_t last = min(first + a.chunk, a.n_items);
+    for (uint32_t it = first; it < last; ++it) {
+      const uint32_t stripe = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it];
+      const uint32_t tile = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it + 1];
+      ConstDescPtr d = (ConstDescPtr)(uintptr_t)(a.stripes + stripe);
+      const uint32_t *prog = d->prog;
+      const uint32_t sl = d->strip_len;
+      // lane b <- pointer of block b, from scalar loads (all 32 entries: the
+      // host zero-fills the unused ones)
+      uint64_t tab = 0;
 #pragma unroll
-    for (int b = 0; b < kMaxBlocks; ++b) {
-      const uint64_t ptr = d->blk[b];
-      tab = lane == (uint32_t)b ? ptr : tab;
-    }
-    for (uint32_t k = 0; k < a.tiles_per_item; ++k) {
-      const uint64_t toff = (uint64_t)(tile + k) * kTileBytes;
-      if (toff >= sl) break;
-      const uint64_t t = tile_table(tab, toff);
-      const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-      if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
+      for (int b = 0; b < kMaxBlocks; ++b) {
+        const uint64_t ptr = d->blk[b];
+        tab = lane == (uint32_t)b ? ptr : tab;
+      }
+      for (uint32_t k = 0; k < a.tiles_per_item; ++k) {
+        const uint64_t toff = (uint64_t)(tile + k) * kTileBytes;
+        if (toff >= sl) break;
+        const uint64_t t = tile_table(tab, toff);
+        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+        if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
+      }
     }
   }
 }
 
 '''
 
-TAIL = r'''int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t stream) {
+TAIL = r'''__global__ void batch_reset_kernel(uint32_t *counter) { *counter = 0u; }
+
+int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t stream) {
   switch (slots) {
 %(EXEC_CASES)s
     default: return -1;
@@ -291,6 +298,7 @@ TAIL = r'''int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t s
 }
 
 int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, stream, a.counter);
   switch (slots) {
 %(BATCH_CASES)s
     default: return -1;
