@@ -254,6 +254,7 @@ __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
   const uint32_t voff = lane * 16u;
   %(DECLS)s
   EC_INIT_%(K)d;
+  uint32_t cur = 0xffffffffu, tab_lo = 0, tab_hi = 0;
   for (;;) {
     uint32_t first = 0;
     if (lane == 0) first = atomicAdd(a.counter, a.chunk);
@@ -266,14 +267,13 @@ __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
       ConstDescPtr d = (ConstDescPtr)(uintptr_t)(a.stripes + stripe);
       const uint32_t *prog = d->prog;
       const uint32_t sl = d->strip_len;
-      // lane b <- pointer of block b, from scalar loads (all 32 entries: the
-      // host zero-fills the unused ones)
-      uint64_t tab = 0;
-#pragma unroll
-      for (int b = 0; b < kMaxBlocks; ++b) {
-        const uint64_t ptr = d->blk[b];
-        tab = lane == (uint32_t)b ? ptr : tab;
+      if (stripe != cur) {
+        // lane b <- pointer of block b, written lane by lane from scalar
+        // loads (all 32 entries: the host zero-fills the unused ones)
+%(WRITELANES)s
+        cur = stripe;
       }
+      const uint64_t tab = ((uint64_t)tab_hi << 32) | tab_lo;
       for (uint32_t k = 0; k < a.tiles_per_item; ++k) {
         const uint64_t toff = (uint64_t)(tile + k) * kTileBytes;
         if (toff >= sl) break;
@@ -325,6 +325,18 @@ int copy_launch(const void *src, void *dst, size_t bytes, hipStream_t stream) {
 '''
 
 
+def writelanes():
+    """Lane b of (tab_lo, tab_hi) <- block b's pointer (v_writelane with an
+    immediate lane: no per-lane compare masks)."""
+    out = []
+    for b in range(32):
+        out.append('        { const uint64_t ptr = d->blk[%d];\n'
+                   '          asm("v_writelane_b32 %%0, %%1, %d" : "+v"(tab_lo) : "s"((uint32_t)ptr));\n'
+                   '          asm("v_writelane_b32 %%0, %%1, %d" : "+v"(tab_hi) : "s"((uint32_t)(ptr >> 32))); }'
+                   % (b, b, b))
+    return "\n".join(out)
+
+
 def init_asm(K):
     regs = ["v_mov_b32_e32 v%d, 0" % r for r in range(4 + 4 * K + 1)]
     return '"' + "\\n\\t".join(regs) + '"'
@@ -335,7 +347,7 @@ def main():
     for K in SLOT_BUDGETS:
         prog = "\n".join('      "%s\\n\\t"                     \\' % l for l in program_asm(K))
         out += PER_K % {"K": K, "INIT": init_asm(K), "OUT": operands(K, "out"), "INOUT": operands(K, "inout"),
-                        "PROGRAM": prog, "CLOB": CLOBBERS, "DECLS": decls(K)}
+                        "PROGRAM": prog, "CLOB": CLOBBERS, "DECLS": decls(K), "WRITELANES": writelanes()}
     exec_cases = "\n".join(
         "    case %d: hipLaunchKernelGGL(slp_exec_kernel_%d, dim3(grid), dim3(256), 0, stream, a); break;" % (K, K)
         for K in SLOT_BUDGETS)
