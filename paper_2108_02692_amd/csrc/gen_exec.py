@@ -244,11 +244,10 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
 }
 
 // Waves take work items from a device counter, `chunk` consecutive items
-// per atomic add (the add's result is a vector memory operation, so taking
-// it waits for the wave's earlier stores: chunks amortise that wait).  An
-// item covers tiles_per_item tiles of its stripe.  Items, descriptors and
-// block tables are read through the scalar cache.  The host lists a
-// stripe's tiles consecutively.
+// per atomic add.  An item covers tiles_per_item tiles of its stripe.
+// Items, descriptors and block tables are read through the scalar cache;
+// the block table is rebuilt only when the stripe changes.  The host lists
+// a stripe's tiles consecutively.
 __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t voff = lane * 16u;
