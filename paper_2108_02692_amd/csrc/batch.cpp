@@ -150,9 +150,14 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     d.n_blocks = (uint32_t)(n_in + n_out);
     d.strip_len = (uint32_t)(st.block_bytes / 8);
     const uint32_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
-    for (uint32_t t = 0; t < n_tiles; t += tiles_per_item) {
+    const uint32_t n_its = (n_tiles + tiles_per_item - 1) / tiles_per_item;
+    // Strips a multiple of 4 MiB apart: consecutive items from 8 distant
+    // segments of the strips (the single-stripe launch does the same).
+    const bool spread = d.strip_len % (4u << 20) == 0 && n_its % 8 == 0;
+    for (uint32_t k = 0; k < n_its; ++k) {
+      const uint32_t i = spread ? (k & 7u) * (n_its >> 3) + (k >> 3) : k;
       items.push_back((uint32_t)s);
-      items.push_back(t);
+      items.push_back(i * tiles_per_item);
     }
     in_bytes += (size_t)n_in * st.block_bytes;
     out_bytes += (size_t)n_out * st.block_bytes;
