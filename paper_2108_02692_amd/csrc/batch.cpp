@@ -53,10 +53,6 @@ namespace {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Waves per SIMD the executor reaches for a slot budget: VGPRs per lane are
-// 4 + 4K + a few of the kernel's own, allocated in granules of 8, out of 512.
-int waves_per_simd(int slots) { return slots <= 24 ? 4 : slots <= 38 ? 3 : 2; }
-
 // Grows the device tables and their pinned staging to hold n_desc stripes
 // and n_words item words (never shrinks).
 ec_status grow(ec_batch *b, size_t n_desc, size_t n_words) {

@@ -40,6 +40,10 @@ struct BatchArgs {
   uint32_t *counter;        // next work item; reset to 0 by the launch itself
 };
 
+// Waves per SIMD the executor reaches for a slot budget: VGPRs per lane are
+// 4 + 4K + a few of the kernel's own, allocated in granules of 8, out of 512.
+inline int waves_per_simd(int slots) { return slots <= 24 ? 4 : slots <= 38 ? 3 : 2; }
+
 // Reset the work counter and launch the persistent kernel for `slots`.
 int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream);
 
