@@ -10,7 +10,7 @@ compressed + fused + scheduled program; the plain bitmatrix program, a
 followed by the batched and the serving workloads and the oracle on the host.
 
 Prints one JSON line (see the keys below).  ``--gpus`` above 1 is refused:
-this build runs on one GPU.
+the executor runs on one GPU.
 """
 from __future__ import annotations
 
@@ -110,8 +110,8 @@ def measured_traffic(prog):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d refused); "
-              "multi-GPU sharding is described in DESIGN.md" % args.gpus, file=sys.stderr)
+        print("bench.py: the executor runs on one GPU; --gpus %d is not supported (stripes would be "
+              "sharded across GPUs by the caller, one process per GPU)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2108_02692_amd as E

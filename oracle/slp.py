@@ -9,7 +9,7 @@ list of terms.  Value semantics are the set semantics of Sec. 4.1: the value
 of a term is a set of constants and XOR is symmetric difference; sets are
 encoded as Python ints used as bitsets over constant indices.
 
-Readings where the paper leaves details open (listed in the design doc):
+Readings where the paper leaves details open:
  * term order (Sec. 4.3): temporaries in creation order come before every
    constant; constants are ordered by index (strip index 8*block + strip);
  * pair frequency counts the original definitions containing both terms;

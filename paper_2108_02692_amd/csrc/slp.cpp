@@ -1,7 +1,7 @@
 // slp.cpp -- bitmatrix expansion, plain SLP, (Xor)RePair, XOR fusion and DFS
 // scheduling (Secs. 1, 2, 4, 5 and 6 of the paper).
 //
-// Readings of points the paper leaves open (also recorded in the design doc):
+// Readings of points the paper leaves open:
 //  * term order: temporaries by creation, all before constants; constants by
 //    strip index 8*block + strip (Sec. 4.3);
 //  * a pair's frequency is the number of original definitions holding both

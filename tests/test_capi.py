@@ -1,6 +1,6 @@
 """The C ABI library on the CPU: it loads, exports every entry point that
 include/ec.h declares, and its gfx950 kernels were built the way the
-executor's design requires (checked on the assembly of this build)."""
+executor's design requires (checked on the assembly of the library built here)."""
 import os
 import re
 import subprocess
@@ -43,7 +43,7 @@ OBJDUMP = os.path.join(os.path.dirname(_build.HIPCC), "..", "llvm", "bin", "llvm
 
 @pytest.fixture(scope="module")
 def built(tmp_path_factory):
-    """Assembly and disassembly of this build's executor (gfx950)."""
+    """Assembly and disassembly of the executor built here (gfx950)."""
     d = tmp_path_factory.mktemp("isa")
     base = [_build.HIPCC, "-x", "hip"] + _build.DEVICE_FLAGS + ["-O3", "-std=c++17", "--cuda-device-only",
                                                                 "-I", os.path.join(ROOT, "include")]
@@ -92,7 +92,7 @@ def test_executor_isa(built):
 
 def test_interpreter_layout(built):
     """The host encodes byte offsets into the executor's tables; check them
-    against this build: handlers 512 bytes apart, 20-byte run steps reading
+    against the built executor: handlers 512 bytes apart, 20-byte run steps reading
     window words 15..2, 16-byte load entries, 8-byte wait entries."""
     _, dis = built
     for K, name in kernel_names():
