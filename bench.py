@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
     ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve",
-                                       "decode_all"],
+                                       "decode_all", "codecs", "small"],
                     default="all",
                     help="time one kernel only (for profiler runs)")
     ap.add_argument("--calib", action="store_true",
@@ -127,6 +127,10 @@ def main():
         return
     if args.only == "decode_all":
         print(json.dumps({"decode_all": bench_decode_all(args, stream)}), flush=True)
+        return
+    if args.only in ("codecs", "small"):
+        print(json.dumps({args.only: (bench_codecs if args.only == "codecs" else bench_small)(args, stream)}),
+              flush=True)
         return
     if args.only == "serve":
         from paper_2108_02692_amd import serve
@@ -260,6 +264,11 @@ def main():
         out["decode_all"] = bench_decode_all(args, stream)
         log("decode all: %.3f ms" % out["decode_all"]["ms"])
         torch.cuda.empty_cache()
+    if args.only == "all":
+        log("codec sweep ...")
+        out["codecs"] = bench_codecs(args, stream)
+        out["small"] = bench_small(args, stream)
+        torch.cuda.empty_cache()
     if args.only == "all" and args.batch_stripes > 0:
         log("batched ...")
         out["batched"] = bench_batched(args, stream)
@@ -275,6 +284,87 @@ def main():
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_block_mib)
     print(json.dumps(out), flush=True)
+
+
+def worst_erasures(n, p, gen):
+    """The set of p data blocks whose decode has the most plain XORs."""
+    import itertools
+    import paper_2108_02692_amd as E
+    best = None
+    for er in itertools.combinations(range(n), p):
+        x = E.ec_compile_slp(n, p, gen, list(er), level=E.LEVEL_PLAIN).info["plain_xor2"]
+        if best is None or x > best[0]:
+            best = (x, list(er))
+    return best[1]
+
+
+def bench_codecs(args, stream):
+    """RS(d,4), RS(d,3) and RS(d,2) for d = 8, 9, 10 (the codecs of the
+    paper's throughput comparison, with Cauchy matrices): encode, and decode
+    of the worst set of p lost data blocks, each compressed and plain, on
+    d blocks of 64 MiB resident in HBM."""
+    import torch
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import workloads as W
+    S = args.block_mib << 20
+    rows = []
+    for p in (4, 3, 2):
+        for n in (8, 9, 10):
+            gen = E.ec_matrix_cauchy(n, p)
+            er = worst_erasures(n, p, gen)
+            data = W.device_blocks(n, S, seed=100 + 10 * n + p)
+            parity = W.empty_blocks(p, S)
+            rec = W.empty_blocks(p, S)
+            row = {"codec": "RS(%d,%d)" % (n, p), "erased": er}
+            ref = None
+            for level, tag in ((E.LEVEL_CO_FU_SCHED, "comp"), (E.LEVEL_PLAIN, "plain")):
+                enc = E.ec_compile_slp(n, p, gen, level=level)
+                ms = time_launches(lambda: E.ec_encode(enc, data, parity, S, stream), args.steps, args.warmup,
+                                   stream)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = [t.clone() for t in parity]
+                elif not all(torch.equal(a, b) for a, b in zip(ref, parity)):
+                    raise SystemExit("bench.py: compressed and plain parity differ for %s" % row["codec"])
+                row["enc_" + tag] = {"ms": ms, "GB_s": n * S / ms / 1e6,
+                                     "hbm_frac": (n + p) * S / ms / 1e6 / HBM_PEAK_GBS,
+                                     "n_xor2": enc.info["n_xor2"], "slots": enc.info["slots"]}
+                dec = E.ec_compile_slp(n, p, gen, er, level=level)
+                blocks = data + ref
+                surv = [blocks[i] for i in dec.in_blocks]
+                ms = time_launches(lambda: E.ec_decode(dec, surv, rec, S, stream), args.steps, args.warmup,
+                                   stream)
+                torch.cuda.synchronize()
+                for j, e in enumerate(dec.out_blocks):
+                    if not torch.equal(rec[j], blocks[e]):
+                        raise SystemExit("bench.py: %s decode self-check failed" % row["codec"])
+                row["dec_" + tag] = {"ms": ms, "GB_s": n * S / ms / 1e6,
+                                     "hbm_frac": (n + len(er)) * S / ms / 1e6 / HBM_PEAK_GBS,
+                                     "n_xor2": dec.info["n_xor2"], "slots": dec.info["slots"]}
+            log("%s: enc %.1f GB/s dec %.1f GB/s" % (row["codec"], row["enc_comp"]["GB_s"],
+                                                      row["dec_comp"]["GB_s"]))
+            rows.append(row)
+            del data, parity, rec, ref, blocks, surv
+            torch.cuda.empty_cache()
+    return rows
+
+
+def bench_small(args, stream):
+    """RS(10,4) encode of 10 x 1 MiB blocks: 14 MiB per launch, which the
+    caches hold and the launch overhead dominates (not a roofline number)."""
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import workloads as W
+    n, p, S = 10, 4, 1 << 20
+    gen = E.ec_matrix_cauchy(n, p)
+    data = W.device_blocks(n, S, seed=0)
+    parity = W.empty_blocks(p, S)
+    res = {"workload": "RS(10,4) encode, 10 x 1 MiB"}
+    for level, tag in ((E.LEVEL_CO_FU_SCHED, "comp"), (E.LEVEL_PLAIN, "plain")):
+        prog = E.ec_compile_slp(n, p, gen, level=level)
+        ms = time_launches(lambda: E.ec_encode(prog, data, parity, S, stream), max(args.steps, 100),
+                           args.warmup, stream)
+        res[tag] = {"ms": ms, "GB_s": n * S / ms / 1e6}
+    return res
 
 
 def bench_batched(args, stream):
