@@ -180,6 +180,16 @@ enum {
  * CO_FU_SCHED. */
 ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, size_t cap, size_t *len);
 
+/* The fused stage (EC_STAGE_FU) scheduled by the bottom-up greedy heuristic
+ * of Sec. 6.6 for an abstract LRU cache of `capacity` entries, in the
+ * export format above, with pebbles for variables: a statement's var is the
+ * pebble its value is put on (pebbles are reused, so a var may be assigned
+ * more than once), operands name pebbles or input strips, and the returned
+ * terms name the pebbles that hold the outputs at the end.  The DFS
+ * heuristic of the same section is EC_STAGE_SCHED.  Needs capacity >= 1 and
+ * a program of level >= EC_LEVEL_CO_FU (else EC_ERR_ARG).  Host-only. */
+ec_status ec_program_export_greedy(const ec_program *prog, int capacity, int32_t *buf, size_t cap, size_t *len);
+
 /* Device-to-device copy with a plain 16-byte-per-lane kernel: the HBM
  * bandwidth ceiling that executor throughput is compared with, and the
  * kernel used to calibrate byte counters.  bytes: multiple of 16; both

@@ -18,7 +18,10 @@ Readings where the paper leaves details open:
    definition only when strictly shorter;
  * fusion (Sec. 5.2) never unfolds a returned variable; repeated operands
    cancel after unfolding; the earliest unfoldable statement is unfolded first;
- * the abstract LRU cache (Sec. 6.2) counts every load and every eviction.
+ * the abstract LRU cache (Sec. 6.2) counts every load and every eviction;
+ * the greedy heuristic (Sec. 6.6) breaks ties among movable cached pebbles by
+   the term order of the variables they hold, and its ratio counts the
+   distinct children of a node.
 """
 from __future__ import annotations
 
@@ -316,6 +319,82 @@ def assign_pebbles(stmts, outputs, is_const):
         out.append((("p", p), pops))
         if v not in goals and v not in last_use:
             free.append(p)
+    ret = [o if (is_const(o) or o == ZERO) else ("p", where[o]) for o in outputs]
+    return out, ret, npeb
+
+
+def greedy_schedule(stmts, outputs, is_const, capacity: int):
+    """Bottom-up greedy heuristic of Sec. 6.6 for an LRU cache of `capacity`
+    entries.  Repeatedly: among the statements whose variable children are
+    computed, take the one with the largest share of children already in the
+    cache (ties to the earliest variable); touch the cached children, then
+    the others, each group in term order; put the result on a movable
+    pebble that is in the cache if there is one, else on any movable pebble,
+    else on a fresh one (movable: it holds a variable that is neither
+    returned nor used again; ties to the earliest held variable).
+    Returns (pebbled statements, returned pebbles, number of pebbles) in the
+    form of ``assign_pebbles``; cache entries are constants and ("p", k)."""
+    def key(t):
+        return (1, t) if is_const(t) else (0, t)
+
+    kids = {}
+    for v, ops in stmts:
+        seen = []
+        for o in ops:
+            if o != ZERO and o not in seen:
+                seen.append(o)
+        kids[v] = seen
+    uses = Counter(o for v in kids for o in kids[v] if not is_const(o))
+    goals = set(o for o in outputs if not is_const(o) and o != ZERO)
+    where = {}   # variable -> pebble
+    holds = {}   # pebble -> variable it holds
+    cache = []   # LRU entry first
+
+    def entry(t):
+        return t if is_const(t) else ("p", where[t])
+
+    def touch(x):
+        if x in cache:
+            cache.remove(x)
+        elif len(cache) >= capacity:
+            cache.pop(0)
+        cache.append(x)
+
+    todo = sorted((v for v, _ in stmts), key=key)
+    out = []
+    npeb = 0
+    while todo:
+        best = None
+        for v in todo:
+            if any(not is_const(o) and o not in where for o in kids[v]):
+                continue
+            h = sum(1 for o in kids[v] if entry(o) in cache)
+            c = len(kids[v])
+            # h/c > bh/bc, with an empty statement scoring 0
+            if best is None or h * best[2] > best[1] * max(c, 1):
+                best = (v, h, max(c, 1))
+        v = best[0]
+        todo.remove(v)
+        hit = sorted((o for o in kids[v] if entry(o) in cache), key=key)
+        miss = sorted((o for o in kids[v] if entry(o) not in cache), key=key)
+        args = [entry(o) for o in hit + miss]
+        for x in args:
+            touch(x)
+        for o in kids[v]:
+            if not is_const(o):
+                uses[o] -= 1
+        movable = [q for q, u in holds.items() if u not in goals and uses[u] == 0]
+        cached = [q for q in movable if ("p", q) in cache]
+        pool = cached or movable
+        if pool:
+            q = min(pool, key=lambda q: key(holds[q]))
+        else:
+            q = npeb
+            npeb += 1
+        touch(("p", q))
+        where[v] = q
+        holds[q] = v
+        out.append((("p", q), args))
     ret = [o if (is_const(o) or o == ZERO) else ("p", where[o]) for o in outputs]
     return out, ret, npeb
 

@@ -86,6 +86,8 @@ def lib():
         L.ec_status_str.restype = ctypes.c_char_p
         L.ec_program_export.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_program_export_greedy.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]
         L.ec_program_bytecode.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
                                           ctypes.POINTER(ctypes.c_size_t)]
         L.ec_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -101,7 +103,7 @@ def lib():
         L.ec_batch_free.argtypes = [vp]
         L.ec_batch_free.restype = None
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
-                     "ec_encode", "ec_decode", "ec_program_export", "ec_program_bytecode", "ec_batch_build", "ec_device_copy",
+                     "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_batch_build", "ec_device_copy",
                      "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set"):
             getattr(L, name).restype = st
         _lib = L
@@ -199,10 +201,21 @@ class Program:
     def export(self, stage: int):
         """Program of one pipeline stage: (stmts, outputs) with terms as in
         ec_program_export (>= 0 variable, -1 zero, <= -2 input strip -t-2)."""
+        return self._exported(lambda buf, cap, n: lib().ec_program_export(self._h, stage, buf, cap, n),
+                              "ec_program_export")
+
+    def export_greedy(self, capacity: int):
+        """The fused stage scheduled by the greedy heuristic for an LRU cache
+        of `capacity` entries: (stmts, outputs) whose variables are pebbles."""
+        return self._exported(lambda buf, cap, n: lib().ec_program_export_greedy(self._h, capacity, buf, cap, n),
+                              "ec_program_export_greedy")
+
+    @staticmethod
+    def _exported(call, what):
         n = ctypes.c_size_t()
-        _check(lib().ec_program_export(self._h, stage, None, 0, ctypes.byref(n)), "ec_program_export")
+        _check(call(None, 0, ctypes.byref(n)), what)
         buf = (ctypes.c_int32 * n.value)()
-        _check(lib().ec_program_export(self._h, stage, buf, n.value, ctypes.byref(n)), "ec_program_export")
+        _check(call(buf, n.value, ctypes.byref(n)), what)
         v = list(buf)
         ns, no = v[0], v[1]
         i = 2

@@ -330,6 +330,20 @@ ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, siz
   return EC_OK;
 }
 
+ec_status ec_program_export_greedy(const ec_program *prog, int capacity, int32_t *buf, size_t cap, size_t *len) {
+  if (!prog || !len || capacity < 1 || prog->level < EC_LEVEL_CO_FU) return EC_ERR_ARG;
+  const_cast<ec_program *>(prog)->paper_stages();
+  std::vector<int32_t> v;
+  try {
+    export_stage(greedy_schedule(prog->fu, capacity), v);
+  } catch (const std::bad_alloc &) {
+    return EC_ERR_NOMEM;
+  }
+  *len = v.size();
+  if (buf) std::memcpy(buf, v.data(), std::min(cap, v.size()) * sizeof(int32_t));
+  return EC_OK;
+}
+
 ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream stream) {
   if (!dst || !src || bytes == 0) return EC_ERR_ARG;
   if (bytes % 16 || !aligned16(dst) || !aligned16(src)) return EC_ERR_ALIGN;

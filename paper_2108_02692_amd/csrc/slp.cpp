@@ -240,6 +240,108 @@ Slp dfs_schedule(const Slp &in) {
   return out;
 }
 
+// ---------------------------------------------------------------- greedy
+Slp greedy_schedule(const Slp &in, int capacity) {
+  // Each step computes one ready node (all variable children computed):
+  // the one whose children are most often already cached, as a fraction of
+  // its distinct children, ties to the earliest variable.  Its children are
+  // touched cached ones first, then the rest, each group in term order, and
+  // its value goes on a dead pebble (holding a variable neither returned nor
+  // used again), a cached one first, ties to the earliest held variable;
+  // else on a fresh pebble.
+  const int ns = (int)in.stmts.size();
+  auto before = [](int a, int b) {
+    const bool ca = is_const(a), cb = is_const(b);
+    return ca != cb ? cb : a < b;  // temporaries before constants, each by number
+  };
+  std::vector<std::vector<int>> kids(ns);
+  std::unordered_map<int, int> uses;
+  for (int i = 0; i < ns; ++i)
+    for (int o : in.stmts[i].ops) {
+      if (o == kZero || std::find(kids[i].begin(), kids[i].end(), o) != kids[i].end()) continue;
+      kids[i].push_back(o);
+      if (!is_const(o)) ++uses[o];
+    }
+  std::set<int> goals;
+  for (int o : in.outputs)
+    if (o != kZero && !is_const(o)) goals.insert(o);
+  std::vector<int> todo(ns);
+  for (int i = 0; i < ns; ++i) todo[i] = i;
+  std::sort(todo.begin(), todo.end(), [&](int a, int b) { return in.stmts[a].var < in.stmts[b].var; });
+
+  // LRU cache of constants (as themselves) and pebbles (q as -(q + 2)),
+  // each with the time of its last touch
+  std::unordered_map<int, long> stamp;
+  long clock = 0;
+  auto touch = [&](int e) {
+    if (!stamp.count(e) && (int)stamp.size() >= capacity) {
+      auto lru = stamp.begin();
+      for (auto it = stamp.begin(); it != stamp.end(); ++it)
+        if (it->second < lru->second) lru = it;
+      stamp.erase(lru);
+    }
+    stamp[e] = ++clock;
+  };
+  std::unordered_map<int, int> peb;  // variable -> pebble
+  std::vector<int> held;             // pebble -> variable on it
+  auto entry = [&](int t) { return is_const(t) ? t : -(peb.at(t) + 2); };
+
+  Slp out;
+  out.n_const = in.n_const;
+  while (!todo.empty()) {
+    int best = -1;
+    long bh = 0, bc = 1;
+    for (int k = 0; k < (int)todo.size(); ++k) {
+      const std::vector<int> &c = kids[todo[k]];
+      bool ready = true;
+      long h = 0;
+      for (int o : c) {
+        if (!is_const(o) && !peb.count(o)) { ready = false; break; }
+        h += stamp.count(entry(o));
+      }
+      if (!ready) continue;
+      const long n = std::max<long>((long)c.size(), 1);
+      if (best < 0 || h * bc > bh * n) { best = k; bh = h; bc = n; }
+    }
+    const int i = todo[best];
+    todo.erase(todo.begin() + best);
+    std::vector<int> hit, miss;
+    for (int o : kids[i]) (stamp.count(entry(o)) ? hit : miss).push_back(o);
+    std::sort(hit.begin(), hit.end(), before);
+    std::sort(miss.begin(), miss.end(), before);
+    hit.insert(hit.end(), miss.begin(), miss.end());
+    Stmt s;
+    for (int o : hit) {
+      touch(entry(o));
+      s.ops.push_back(is_const(o) ? o : peb.at(o));
+    }
+    for (int o : kids[i])
+      if (!is_const(o)) --uses[o];
+    int pick = -1;
+    bool pick_cached = false;
+    for (int q = 0; q < (int)held.size(); ++q) {
+      const int u = held[q];
+      if (goals.count(u) || uses[u] != 0) continue;
+      const bool c = stamp.count(-(q + 2)) != 0;
+      if (pick < 0 || (c && !pick_cached) || (c == pick_cached && before(u, held[pick]))) {
+        pick = q;
+        pick_cached = c;
+      }
+    }
+    if (pick < 0) {
+      pick = (int)held.size();
+      held.push_back(0);
+    }
+    touch(-(pick + 2));
+    held[pick] = in.stmts[i].var;
+    peb[in.stmts[i].var] = pick;
+    s.var = pick;
+    out.stmts.push_back(std::move(s));
+  }
+  for (int o : in.outputs) out.outputs.push_back(o == kZero || is_const(o) ? o : peb.at(o));
+  return out;
+}
+
 // ---------------------------------------------------------------- measures
 std::vector<Bits> evaluate(const Slp &p) {
   std::unordered_map<int, Bits> env;

@@ -65,6 +65,12 @@ Slp fuse(const Slp &in);
 // DFS post-order over the computation graph (Sec. 6.6).
 Slp dfs_schedule(const Slp &in);
 
+// Bottom-up greedy heuristic (Sec. 6.6) for an LRU cache of `capacity`
+// entries.  The result assigns pebbles: every statement's var is a pebble
+// number (pebbles are reassigned), operands name pebbles or constants, and
+// the outputs name the pebbles holding the returned values at the end.
+Slp greedy_schedule(const Slp &in, int capacity);
+
 // Set-semantics value of every returned term.
 std::vector<Bits> evaluate(const Slp &p);
 

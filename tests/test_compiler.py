@@ -2,8 +2,9 @@
 
 * bitmatrix / plain program: equal to the oracle's bitmatrix of the same
   generator (the one deliberate cross-check of Sec. 1 (ii) between the two);
-* XorRePair, fusion, DFS stages: statement-for-statement equal to the
-  oracle's implementation of Secs. 4-6 (same readings of the tie-breaks);
+* XorRePair, fusion, DFS stages and the greedy schedule: statement-for-
+  statement equal to the oracle's implementation of Secs. 4-6 (same
+  readings of the tie-breaks);
 * the executed program and its device bytecode: the bitmatrix rows under the
   set semantics of Sec. 4.1, checked by the independent bytecode simulator;
 * error handling of ec_compile_slp.
@@ -127,6 +128,39 @@ def test_paper_matrix_stages_equal_oracle():
     prog = E.ec_compile_slp(10, 4, gen)
     assert to_oracle_terms(*prog.export(E.STAGE_CO)) == (co_st, co_out)
     assert to_oracle_terms(*prog.export(E.STAGE_SCHED))[0] == dfs
+
+
+def pebbled(stmts, outs):
+    """Library greedy export -> the oracle's pebbled form."""
+    t = lambda x: BIG + (-x - 2) if x <= -2 else ("p", x)
+    return [(("p", v), [t(o) for o in ops]) for v, ops in stmts], [t(o) for o in outs]
+
+
+@pytest.mark.parametrize("n,p,er,mat", [
+    (10, 4, (), "cauchy"), (10, 4, (2, 4, 5, 6), "cauchy"), (6, 3, (1, 7), "cauchy"), (10, 4, (), "vandermonde"),
+    (10, 4, (2, 4, 5, 6), "vandermonde")])
+def test_greedy_schedule_equals_oracle(n, p, er, mat):
+    gen = (E.ec_matrix_cauchy if mat == "cauchy" else E.ec_matrix_vandermonde)(n, p)
+    rows = oracle_rows(gen, n, p, er)
+    (_, outs), fu, _ = oracle_pipeline(rows, 8 * n)
+    prog = E.ec_compile_slp(n, p, gen, er)
+    isc = lambda t: isinstance(t, int) and t >= BIG
+    want = S.evaluate(fu, outs, 0, isc)
+    for cap in (4, 8, 32, 128, 1000):
+        peb, ret, npeb = S.greedy_schedule(fu, outs, isc, cap)
+        got, got_ret = pebbled(*prog.export_greedy(cap))
+        assert got == peb and got_ret == ret
+        assert S.evaluate(got, got_ret, 0, isc) == want
+
+
+def test_greedy_export_errors():
+    gen = E.ec_matrix_cauchy(6, 3)
+    with pytest.raises(E.EcError, match="EC_ERR_ARG"):
+        E.ec_compile_slp(6, 3, gen).export_greedy(0)
+    for level in (E.LEVEL_PLAIN, E.LEVEL_CO):
+        with pytest.raises(E.EcError, match="EC_ERR_ARG"):
+            E.ec_compile_slp(6, 3, gen, level=level).export_greedy(8)
+    assert E.ec_compile_slp(6, 3, gen, level=E.LEVEL_CO_FU).export_greedy(8)[0]
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])

@@ -189,14 +189,9 @@ def test_P_eg_iocost_at_capacity_10():
 
 def test_dfs_reproduces_Q_DFS():
     # G_eg with the figure's goals; children and roots visited by variable
-    cmap = {x: i for i, x in enumerate("ABCDEFG")}
     isc = lambda t: t >= 1000
-    names = {}
-    prog = []
-    for v, ops in G_LRU["programs"]["P_eg"]:
-        names[v] = len(names) + 1
-        prog.append((names[v], [1000 + cmap[o] if o in cmap else names[o] for o in ops]))
-    goals = [names[v] for v in G_LRU["dfs"]["goals"]]
+    prog, goals, _ = g_eg()
+    names = {v: i + 1 for i, (v, _) in enumerate(G_LRU["programs"]["P_eg"])}
     order = S.dfs_order(prog, goals, isc)
     inv = {i: v for v, i in names.items()}
     assert [inv[v] for v, _ in order] == G_LRU["dfs"]["order"]
@@ -204,6 +199,61 @@ def test_dfs_reproduces_Q_DFS():
     assert npeb == G_LRU["dfs"]["pebbles"]
     # the pebbles the DFS schedule assigns are the printed Q_DFS's variables
     assert ["p%d" % (pebble[1] + 1) for pebble, _ in peb] == [v for v, _ in G_LRU["programs"]["Q_DFS"]]
+
+
+def g_eg():
+    """G_eg in integer terms: constants A..G = 1000.., variables v1..v5 = 1..5."""
+    cmap = {x: 1000 + i for i, x in enumerate("ABCDEFG")}
+    names = {}
+    prog = []
+    for v, ops in G_LRU["programs"]["P_eg"]:
+        names[v] = len(names) + 1
+        prog.append((names[v], [cmap[o] if o in cmap else names[o] for o in ops]))
+    goals = [names[v] for v in G_LRU["dfs"]["goals"]]
+    return prog, goals, {c: x for x, c in cmap.items()}
+
+
+def test_greedy_reproduces_Q_greedy():
+    # Sec. 6.6 worked example: capacity 8, the figure's goals
+    prog, goals, cname = g_eg()
+    peb, ret, npeb = S.greedy_schedule(prog, goals, lambda t: t >= 1000, 8)
+    show = lambda a: cname[a] if isinstance(a, int) else "p%d" % (a[1] + 1)
+    got = [[show(p), [show(a) for a in args]] for p, args in peb]
+    assert got == G_LRU["programs"]["Q_greedy"]
+    assert npeb == G_LRU["nvar"]["Q_greedy"]
+    assert S.ccap(peb) == G_LRU["ccap"]["Q_greedy"]
+    assert S.iocost(peb, 8) == G_LRU["iocost_8"]["Q_greedy"]
+    # the goals v2, v3, v5 end on the pebbles the printed program leaves them on
+    assert [show(r) for r in ret] == ["p3", "p2", "p1"]
+
+
+def random_program(rng, n_const, n_stmt):
+    stmts = []
+    for v in range(n_stmt):
+        pool = list(range(1000, 1000 + n_const)) + list(range(v))
+        stmts.append((v, rng.sample(pool, rng.randint(2, min(5, len(pool))))))
+    used = {o for _, ops in stmts for o in ops}
+    goals = [v for v, _ in stmts if v not in used or rng.random() < 0.2]
+    return stmts, goals
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_greedy_keeps_meaning_and_pebbles(seed):
+    rng = random.Random(seed)
+    stmts, goals = random_program(rng, 12, 30)
+    isc = lambda t: isinstance(t, int) and t >= 1000
+    want = S.evaluate(stmts, goals, 0, isc)
+    for cap in (4, 8, 64):
+        peb, ret, npeb = S.greedy_schedule(stmts, goals, isc, cap)
+        assert len(peb) == len(stmts)
+        assert S.evaluate(peb, ret, 0, isc) == want
+        assert S.nvar(peb) == npeb <= len(stmts)
+        # distinct goals end on distinct pebbles
+        assert len({r for r in ret if not isc(r)}) == len(set(goals))
+    # with room for everything every constant is loaded once and nothing is evicted
+    peb, _, _ = S.greedy_schedule(stmts, goals, isc, 10 ** 6)
+    loads, ev, re = S.lru_run(peb, 10 ** 6)
+    assert ev == 0 and re == 0 and loads == len({o for _, ops in stmts for o in ops if isc(o)})
 
 
 # ---- Sec. 7.5: printed counts of the paper's RS(10,4) programs
@@ -247,3 +297,31 @@ def test_paper_compress_fuse_counts_approx(paper_enc_rows, paper_dec_rows):
         assert within(len(fused), ref["fused_statements"], tol["fused_statements"]), len(fused)
         assert within(S.count_mem(fused), ref["fused_memory_accesses"], tol["fused_memory_accesses"])
         assert S.count_xor(fused) == comp.xor_count()
+
+
+G_SCHED = golden("rs10_4_schedule_measures")
+
+
+@pytest.mark.slow
+def test_paper_schedule_measures_approx(paper_enc_rows, paper_dec_rows):
+    tol = G_SCHED["tolerance"]
+    about = G_SCHED["about_every_block_size"]
+    for rows, ref, name in ((paper_enc_rows, G_SCHED["dfs"]["encode"], "enc"),
+                            (paper_dec_rows, G_SCHED["dfs"]["decode_2_4_5_6"], "dec")):
+        comp = S.repair(rows, 80, xor_rebuild=True)
+        stmts, outs = comp.to_program()
+        fused = S.fuse(stmts, outs, comp.is_const)
+        order = S.dfs_order(fused, outs, comp.is_const)
+        peb, _, npeb = S.assign_pebbles(order, outs, comp.is_const)
+        assert within(npeb, ref["nvar"], tol["dfs_nvar"]), (name, npeb)
+        assert within(S.ccap(peb), ref["ccap"], tol["dfs_ccap"]), (name, S.ccap(peb))
+        if name != "enc":
+            continue
+        assert within(npeb, about["nvar"], tol["about_nvar"]) and within(S.ccap(peb), about["ccap"], tol["about_ccap"])
+        for b in about["block_bytes"]:
+            cap = about["l1_bytes"] // b
+            g, ret, gn = S.greedy_schedule(fused, outs, comp.is_const, cap)
+            isc = lambda t: isinstance(t, int) and comp.is_const(t)
+            assert S.evaluate(g, ret, 80, isc) == S.evaluate(fused, outs, 80, comp.is_const)
+            assert within(gn, about["nvar"], tol["about_nvar"]), (b, gn)
+            assert within(S.ccap(g), about["ccap"], tol["about_ccap"]), (b, S.ccap(g))
