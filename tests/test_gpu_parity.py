@@ -89,13 +89,16 @@ def test_encode_ragged_sizes(S):
         assert_blocks_equal(run_encode(prog, data, S), want, "encode S=%d level %d" % (S, level))
 
 
-@pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])
+CODECS = [(6, 3), (12, 4), (14, 4), (8, 4), (9, 4), (8, 3), (9, 3), (10, 3), (8, 2), (9, 2), (10, 2)]
+
+
+@pytest.mark.parametrize("n,p", CODECS)
 def test_encode_other_codecs(n, p):
     S = 64 * 1024
     gen = E.ec_matrix_cauchy(n, p)
     data = W.host_blocks(n, S, seed=n * 10 + p)
     want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
-    for K in (24, 48):
+    for K in (0, 24, 48):
         prog = E.ec_compile_slp(n, p, gen, slot_budget=K)
         assert_blocks_equal(run_encode(prog, data, S), want, "RS(%d,%d) K %d" % (n, p, K))
 
@@ -182,7 +185,7 @@ def test_decode_rs10_4_1mib(er, level):
     assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], "decode %s" % (er,))
 
 
-@pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])
+@pytest.mark.parametrize("n,p", CODECS)
 def test_decode_other_codecs_sampled(n, p):
     S = 4096
     gen = E.ec_matrix_cauchy(n, p)
@@ -211,6 +214,32 @@ def test_encode_64mib_sampled():
         want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, mini)
         got = [W.strip_sample(b, offs, 16).cpu().numpy() for b in par]
         assert_blocks_equal(got, want, "64 MiB level %d" % level)
+
+
+@pytest.mark.parametrize("er", [(4, 5, 6, 7), (2, 4, 5, 6), (0, 11, 13)])
+def test_decode_64mib_sampled(er):
+    """Decode at the benchmark's block size (10 x 64 MiB, default program),
+    in the launch the benchmark times: every erased block checked on sampled
+    strip offsets against the oracle's decode of the same samples."""
+    n, p, S = 10, 4, 64 << 20
+    gen = E.ec_matrix_cauchy(n, p)
+    G = np.array(gen, dtype=np.uint8)
+    data = W.device_blocks(n, S, seed=12)
+    par = W.empty_blocks(p, S)
+    E.ec_encode(E.ec_compile_slp(n, p, gen), data, par, S)
+    blocks = data + par
+    prog = E.ec_compile_slp(n, p, gen, list(er))
+    rec = W.empty_blocks(len(er), S, fill=0xA5)
+    E.ec_decode(prog, [blocks[i] for i in prog.in_blocks], rec, S)
+    torch.cuda.synchronize()
+    L = S // 8
+    offs = [0, 2048, L // 3 + 16, L - 1024, L - 16]
+    mini = [W.strip_sample(b, offs, 16).cpu().numpy() for b in blocks[:n]]
+    mini = mini + oracle.encode(G, n, p, mini)
+    want = oracle.decode(G, n, p, list(er), [None if i in er else mini[i] for i in range(n + p)])
+    got = [W.strip_sample(r, offs, 16).cpu().numpy() for r in rec]
+    assert_blocks_equal(got, [want[list(er).index(e)] for e in prog.out_blocks], "64 MiB decode %s" % (er,))
+    assert_blocks_equal(got, [mini[e] for e in prog.out_blocks], "64 MiB decode %s vs data" % (er,))
 
 
 def test_outputs_fully_written_and_inputs_untouched():
