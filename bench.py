@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--batch-max-mib", type=int, default=4, help="largest block of the batched workload (MiB)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of Poisson arrivals (0 = skip)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--decode-all-slots", type=int, default=44, help="slot budget of the every-erasure-set decode")
     ap.add_argument("--sweep", action="store_true",
                     help="time every (level, slot budget) pair on the workload and print one line each")
     ap.add_argument("--sweep-prefetch", action="store_true", help="with --sweep: also vary the prefetch distance")
@@ -428,7 +429,8 @@ def bench_decode_all(args, stream):
     g.manual_seed(17)
     data = torch.randint(0, 256, (P, n, S), dtype=torch.uint8, device="cuda", generator=g)
     parity = torch.empty((P, p, S), dtype=torch.uint8, device="cuda")
-    cache = batching.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=38)
+    K = args.decode_all_slots
+    cache = batching.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=K)
     enc = cache.get(n, p)
     encode = E.ec_batch_build([(enc, list(data[k]), list(parity[k]), S) for k in range(P)], stream=stream)
     encode.launch(stream)
@@ -449,7 +451,7 @@ def bench_decode_all(args, stream):
         raise SystemExit("bench.py: decode-all self-check failed")
     in_bytes = P * n * S
     res = {"patterns": P, "block_bytes": S, "ms": ms, "GB_s": in_bytes / ms / 1e6,
-           "hbm_frac": (in_bytes + n_out * S) / ms / 1e6 / HBM_PEAK_GBS, "slots": 38, "verified": ok}
+           "hbm_frac": (in_bytes + n_out * S) / ms / 1e6 / HBM_PEAK_GBS, "slots": K, "verified": ok}
     encode.free()
     batch.free()
     del data, parity, out
