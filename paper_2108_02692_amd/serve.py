@@ -214,7 +214,7 @@ def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool
     return reqs
 
 
-def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=512):
+def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=512, slots=38):
     """The serving benchmark: returns throughput and latency percentiles."""
     import torch
     pool_bytes = 1 << 30
@@ -222,7 +222,7 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     g.manual_seed(seed)
     pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
     t_setup = time.perf_counter()
-    server = Server(budget_bytes=budget_bytes, n_slots=n_slots, max_batch=max_batch)
+    server = Server(budget_bytes=budget_bytes, n_slots=n_slots, max_batch=max_batch, slots=slots)
     setup_s = time.perf_counter() - t_setup
     reqs = make_requests(duration_s, rate, seed, pool.data_ptr(), pool_bytes)
     torch.cuda.synchronize()
