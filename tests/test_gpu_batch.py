@@ -97,3 +97,65 @@ def test_reusable_batch_reserve_and_refill():
         torch.cuda.synchronize()
         check(outs, want, "refill seed %d" % seed)
     batch.free()
+
+
+def test_batch_edge_shapes_and_mixed_levels():
+    """One batch holding the extremes: the widest codec (32 blocks), 1-block
+    codecs, blocks of 128 B (one lane of one tile per strip) and ragged
+    sizes, encodes and decodes, programs of different levels at one slot
+    budget; two inputs shared read-only by several stripes."""
+    rng = np.random.default_rng(31)
+    cases = [(28, 4, (), 128), (1, 1, (), 128), (1, 1, (0,), 256), (2, 1, (1,), 384), (10, 4, (2, 4, 5, 6), 1152),
+             (6, 3, (), 3 * 8192 + 128), (14, 4, (0, 13), 4096 + 128), (10, 4, (), 128), (12, 4, (15,), 8 * 1024 * 9)]
+    stripes, want, keep = [], [], []
+    for k, (n, p, er, S) in enumerate(cases):
+        gen = E.ec_matrix_cauchy(n, p)
+        G = np.array(gen, dtype=np.uint8)
+        level = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU_SCHED)[k % 3]
+        prog = E.ec_compile_slp(n, p, gen, list(er), level=level, slot_budget=44)
+        data = [rng.integers(0, 256, S, dtype=np.uint8) for _ in range(n)]
+        blocks = data + oracle.encode(G, n, p, data)
+        if er:
+            ins = W.to_device([blocks[i] for i in prog.in_blocks])
+            exp = [blocks[e] for e in er]
+        else:
+            ins = W.to_device(data)
+            exp = blocks[n:]
+        outs = W.empty_blocks(len(exp), S, fill=0xA5)
+        stripes.append((prog, ins, outs, S))
+        want.append(exp)
+        keep.append(prog)
+        if k == 4:  # the same inputs again, as a second stripe with its own outputs
+            outs2 = W.empty_blocks(len(exp), S, fill=0xA5)
+            stripes.append((prog, ins, outs2, S))
+            want.append(exp)
+    stream = torch.cuda.current_stream()
+    batch = E.ec_batch_build(stripes, stream=stream)
+    for rep in range(2):
+        for _, _, outs, _ in stripes:
+            for t in outs:
+                t.fill_(0x11 * (rep + 1))
+        torch.cuda.synchronize()
+        batch.launch(stream)
+        torch.cuda.synchronize()
+        check([o for _, _, o, _ in stripes], want, "edge batch replay %d" % rep)
+    batch.free()
+
+
+def test_batch_argument_errors():
+    gen = E.ec_matrix_cauchy(6, 3)
+    prog = E.ec_compile_slp(6, 3, gen, slot_budget=38)
+    d = W.empty_blocks(6, 4096, fill=0)
+    o = W.empty_blocks(3, 4096)
+    with pytest.raises(E.EcError) as e:
+        E.ec_batch_build([])
+    assert e.value.name == "EC_ERR_ARG"
+    with pytest.raises(E.EcError) as e:  # block size not a multiple of 128
+        E.ec_batch_build([(prog, d, o, 4096 - 64)])
+    assert e.value.name == "EC_ERR_ALIGN"
+    with pytest.raises(E.EcError) as e:  # an output aliasing an input
+        E.ec_batch_build([(prog, d, [d[0], o[1], o[2]], 4096)])
+    assert e.value.name == "EC_ERR_ARG"
+    with pytest.raises(E.EcError) as e:  # work items of 1.5 KiB
+        E.ec_batch_build([(prog, d, o, 4096)], tile_bytes=1536)
+    assert e.value.name == "EC_ERR_UNSUPPORTED"
