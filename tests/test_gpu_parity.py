@@ -242,6 +242,34 @@ def test_decode_64mib_sampled(er):
     assert_blocks_equal(got, [mini[e] for e in prog.out_blocks], "64 MiB decode %s vs data" % (er,))
 
 
+def test_largest_block_sampled():
+    """The largest block the executor takes (4 GiB - 128 B: strips of just
+    under 512 MiB, strip offsets past 2^31 within a block), RS(4,2) encode
+    and a two-block decode, checked on sampled strip offsets against the
+    oracle."""
+    n, p, S = 4, 2, (1 << 32) - 128
+    gen = E.ec_matrix_cauchy(n, p)
+    G = np.array(gen, dtype=np.uint8)
+    data = W.device_blocks(n, S, seed=13)
+    par = W.empty_blocks(p, S, fill=0xA5)
+    E.ec_encode(E.ec_compile_slp(n, p, gen), data, par, S)
+    torch.cuda.synchronize()
+    L = S // 8
+    offs = [0, 1024, L // 2 + 48, L - 1024, L - 16]
+    blocks = data + par
+    mini = [W.strip_sample(b, offs, 16).cpu().numpy() for b in blocks]
+    assert_blocks_equal(mini[n:], oracle.encode(G, n, p, mini[:n]), "largest block encode")
+    er = [0, 3]
+    prog = E.ec_compile_slp(n, p, gen, er)
+    rec = W.empty_blocks(len(er), S, fill=0xA5)
+    E.ec_decode(prog, [blocks[i] for i in prog.in_blocks], rec, S)
+    torch.cuda.synchronize()
+    got = [W.strip_sample(r, offs, 16).cpu().numpy() for r in rec]
+    assert_blocks_equal(got, [mini[e] for e in prog.out_blocks], "largest block decode")
+    del data, par, rec, blocks
+    torch.cuda.empty_cache()
+
+
 def test_outputs_fully_written_and_inputs_untouched():
     n, p, S = 10, 4, 4096 + 128
     gen = E.ec_matrix_cauchy(n, p)
