@@ -214,7 +214,10 @@ typedef struct {
  * stripes' buffers and programs must stay valid for every later launch.
  * tile_bytes: bytes per strip one work item covers (a multiple of 1024, the
  * bytes of a strip one wave handles per tile; 0 = 1024).  Programs in one
- * batch must share one slot budget (EC_ERR_UNSUPPORTED otherwise). */
+ * batch must share one slot budget (EC_ERR_UNSUPPORTED otherwise).  The
+ * stripes run in no defined order, so every output block must be disjoint
+ * from every other output block and from every input block of the batch
+ * (EC_ERR_ARG otherwise); input blocks may be shared between stripes. */
 ec_status ec_batch_build(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
                          ec_batch **out);
 

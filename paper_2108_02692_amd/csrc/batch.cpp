@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <memory>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/ec.h"
@@ -52,6 +53,33 @@ struct ec_batch {
 namespace {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// The stripes of one launch run in no defined order, so every byte written
+// must be written by one output block only and read by none: the written
+// ranges are pairwise disjoint and disjoint from every read range (reads
+// may overlap each other).  Ranges are [begin, end).
+bool disjoint_writes(std::vector<std::pair<uintptr_t, uintptr_t>> &reads,
+                     std::vector<std::pair<uintptr_t, uintptr_t>> &writes) {
+  std::sort(writes.begin(), writes.end());
+  for (size_t k = 1; k < writes.size(); ++k)
+    if (writes[k].first < writes[k - 1].second) return false;
+  // merge the read ranges, then look up each write among them
+  std::sort(reads.begin(), reads.end());
+  std::vector<std::pair<uintptr_t, uintptr_t>> merged;
+  for (const auto &r : reads) {
+    if (!merged.empty() && r.first <= merged.back().second)
+      merged.back().second = std::max(merged.back().second, r.second);
+    else
+      merged.push_back(r);
+  }
+  for (const auto &w : writes) {
+    // first merged read range ending after the write begins
+    auto it = std::upper_bound(merged.begin(), merged.end(), w.first,
+                               [](uintptr_t x, const std::pair<uintptr_t, uintptr_t> &r) { return x < r.second; });
+    if (it != merged.end() && it->first < w.second) return false;
+  }
+  return true;
+}
 
 // Grows the device tables and their pinned staging to hold n_desc stripes
 // and n_words item words (never shrinks).
@@ -113,6 +141,8 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return EC_ERR_DEVICE;
   std::vector<StripeDesc> desc((size_t)n_stripes);
   std::vector<uint32_t> items;
+  // byte ranges read and written by the whole launch
+  std::vector<std::pair<uintptr_t, uintptr_t>> reads, writes;
   int slots = 0;
   size_t in_bytes = 0, out_bytes = 0;
   for (int s = 0; s < n_stripes; ++s) {
@@ -129,16 +159,13 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
       if (!st.in[i]) return EC_ERR_ARG;
       if (!aligned16(st.in[i])) return EC_ERR_ALIGN;
       d.blk[i] = (uint64_t)(uintptr_t)st.in[i];
+      reads.push_back({(uintptr_t)st.in[i], (uintptr_t)st.in[i] + st.block_bytes});
     }
     for (int j = 0; j < n_out; ++j) {
       if (!st.out[j]) return EC_ERR_ARG;
       if (!aligned16(st.out[j])) return EC_ERR_ALIGN;
-      const uintptr_t a = (uintptr_t)st.out[j];
-      for (int i = 0; i < n_in; ++i) {
-        const uintptr_t c = (uintptr_t)st.in[i];
-        if (a < c + st.block_bytes && c < a + st.block_bytes) return EC_ERR_ARG;
-      }
-      d.blk[n_in + j] = (uint64_t)a;
+      d.blk[n_in + j] = (uint64_t)(uintptr_t)st.out[j];
+      writes.push_back({(uintptr_t)st.out[j], (uintptr_t)st.out[j] + st.block_bytes});
     }
     ec_status ws = EC_OK;
     d.prog = const_cast<ec_program *>(prog)->device_words(&ws);
@@ -159,6 +186,7 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     out_bytes += (size_t)n_out * st.block_bytes;
   }
   if (items.size() / 2 > 0xFFFFFFFFull) return EC_ERR_UNSUPPORTED;
+  if (!disjoint_writes(reads, writes)) return EC_ERR_ARG;
   ec_status gs = grow(b, desc.size(), items.size());
   if (gs != EC_OK) return gs;
   std::copy(desc.begin(), desc.end(), b->h_desc);

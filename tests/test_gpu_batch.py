@@ -156,6 +156,21 @@ def test_batch_argument_errors():
     with pytest.raises(E.EcError) as e:  # an output aliasing an input
         E.ec_batch_build([(prog, d, [d[0], o[1], o[2]], 4096)])
     assert e.value.name == "EC_ERR_ARG"
+    o2 = W.empty_blocks(3, 4096)
+    with pytest.raises(E.EcError) as e:  # two stripes writing the same block
+        E.ec_batch_build([(prog, d, o, 4096), (prog, d, [o2[0], o[1], o2[2]], 4096)])
+    assert e.value.name == "EC_ERR_ARG"
+    with pytest.raises(E.EcError) as e:  # a stripe reading what another writes
+        E.ec_batch_build([(prog, d, o, 4096), (prog, [o[2]] + d[1:], o2, 4096)])
+    assert e.value.name == "EC_ERR_ARG"
+    half = torch.empty(2 * 4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.EcError) as e:  # outputs overlapping by half a block
+        E.ec_batch_build([(prog, d, [half[:4096], o[1], o[2]], 4096),
+                          (prog, d, [half[2048:6144], o2[1], o2[2]], 4096)])
+    assert e.value.name == "EC_ERR_ARG"
+    # shared inputs and back-to-back outputs are fine
+    E.ec_batch_build([(prog, d, [half[:4096], o[1], o[2]], 4096),
+                      (prog, d, [half[4096:], o2[1], o2[2]], 4096)]).free()
     with pytest.raises(E.EcError) as e:  # work items of 1.5 KiB
         E.ec_batch_build([(prog, d, o, 4096)], tile_bytes=1536)
     assert e.value.name == "EC_ERR_UNSUPPORTED"
