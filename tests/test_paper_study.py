@@ -67,3 +67,46 @@ def test_average_reduction_ratios_match_printed():
     got = {"co_over_p": co_p, "fu_over_p": fu_p, "fuco_over_co": fuco_co, "fuco_over_p": fuco_p}
     for k, v in got.items():
         assert abs(v - ref["mem_ratio"][k]) <= tol, (k, v, ref["mem_ratio"][k])
+
+
+# ---- Sec. 7.5 figure: measures of the optimised programs for RS(d,p)
+FIG = json.load(open(os.path.join(os.path.dirname(GOLDEN), "rs_codecs_paper_figure.json")))
+
+
+def _within(x, ref, band):
+    return ref * (1 + band[0]) <= x <= ref * (1 + band[1])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("codec", sorted(FIG["codecs"]))
+def test_codec_figure_measures(codec):
+    """The oracle's pipeline (XorRePair, fusion, DFS and its pebbles, the LRU
+    CCap) on the paper's matrix for each codec of the figure, pinned to the
+    printed values within the fixture's bands; the library's whole-matrix
+    stages for the same programs equal the oracle's statement for
+    statement."""
+    from oracle import slp as S
+    d, p = map(int, codec.split(","))
+    ref = dict(zip(FIG["columns"], FIG["codecs"][codec]))
+    tol = FIG["tolerance"]
+    G = oracle.vandermonde_rows(d, p)
+    er = [2, 4, 5, 6][:p]
+    D, _ = oracle.decode_matrix(G, d, p, er)
+    gen = G.tolist()
+    big = S.Compressed.BIG
+    term = lambda x: S.ZERO if x == -1 else (big + (-x - 2) if x <= -2 else x)
+    for tag, mat, erased in (("enc", G[d:], ()), ("dec", D, er)):
+        rows = S.rows_from_bitmatrix(oracle.bitmatrix(mat))
+        comp = S.repair(rows, 8 * d, xor_rebuild=True)
+        st, outs = comp.to_program()
+        fu = S.fuse(st, outs, comp.is_const)
+        order = S.dfs_order(fu, outs, comp.is_const)
+        peb, _, npeb = S.assign_pebbles(order, outs, comp.is_const)
+        got = {"stmt": len(fu), "mem": S.count_mem(fu), "nvar": npeb, "ccap": S.ccap(peb)}
+        for k, v in got.items():
+            assert _within(v, ref["%s_%s" % (k, tag)], tol[k]), (codec, tag, k, v, ref["%s_%s" % (k, tag)])
+        prog = E.ec_compile_slp(d, p, gen, list(erased))
+        pfu, pouts = prog.export(E.STAGE_FU)
+        assert [(v, [term(o) for o in ops]) for v, ops in pfu] == fu and [term(o) for o in pouts] == outs
+        psched, _ = prog.export(E.STAGE_SCHED)
+        assert [(v, [term(o) for o in ops]) for v, ops in psched] == order
