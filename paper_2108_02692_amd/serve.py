@@ -159,10 +159,14 @@ class Server:
                 s["reqs"] = None
         return done
 
-    def serve(self, requests, t0=None, realtime=True, on_done=None):
+    def serve(self, requests, t0=None, realtime=True, on_done=None, idle_sleep_s=0.0):
         """Run requests (sorted by arrival) to completion; returns wall time.
         ``on_done(reqs)`` sees each finished batch while its outputs are still
-        in the arena; ``realtime=False`` admits every request at once."""
+        in the arena; ``realtime=False`` admits every request at once.
+        ``idle_sleep_s``: pause when nothing can be done.  The default 0 keeps
+        polling, which holds one host core; a sleep of even 20 us costs its
+        own wake-up latency twice per request (measured at 20k req/s: p50
+        0.135 ms with it, 0.071 ms polling)."""
         now_fn = (lambda: time.perf_counter() - t0)
         if t0 is None:
             t0 = time.perf_counter()
@@ -184,8 +188,8 @@ class Server:
                 if batch:
                     self.launch(slot, batch)
                     continue
-            if slot is None or i >= n or requests[i].arrival > now_fn():
-                time.sleep(2e-5)
+            if idle_sleep_s > 0 and (slot is None or i >= n or requests[i].arrival > now_fn()):
+                time.sleep(idle_sleep_s)
         return now_fn()
 
 
@@ -214,7 +218,8 @@ def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool
     return reqs
 
 
-def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=512, slots=38):
+def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=512, slots=38,
+        idle_sleep_s=0.0):
     """The serving benchmark: returns throughput and latency percentiles."""
     import torch
     pool_bytes = 1 << 30
@@ -231,7 +236,7 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     gc.collect()
     gc.disable()
     try:
-        wall = server.serve(reqs)
+        wall = server.serve(reqs, idle_sleep_s=idle_sleep_s)
     finally:
         gc.enable()
     torch.cuda.synchronize()
@@ -245,7 +250,7 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     gc.collect()
     gc.disable()
     try:
-        drain = server.serve(reqs, realtime=False)
+        drain = server.serve(reqs, realtime=False, idle_sleep_s=idle_sleep_s)
     finally:
         gc.enable()
     torch.cuda.synchronize()
