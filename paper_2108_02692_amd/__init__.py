@@ -19,11 +19,12 @@ __all__ = [
     "EcError", "Program", "ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp",
     "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_device_copy", "lib",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
-    "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC",
+    "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
 ]
 
 LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
 COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
+SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS = 0, 1, 2
 STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
 
 STATUS = {
@@ -47,13 +48,13 @@ DEFAULT_PREFETCH = 0
 class CompileOpts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("slot_budget", ctypes.c_uint32),
                 ("compress", ctypes.c_uint32), ("block_strips", ctypes.c_uint32),
-                ("prefetch", ctypes.c_uint32)]
+                ("prefetch", ctypes.c_uint32), ("split", ctypes.c_uint32)]
 
 
 class ProgramInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
-        "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words")] + [
+        "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
 
 
@@ -90,6 +91,8 @@ def lib():
                                                ctypes.POINTER(ctypes.c_size_t)]
         L.ec_program_bytecode.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_program_part_bytecode.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
+                                               ctypes.POINTER(ctypes.c_size_t)]
         L.ec_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.ec_program_upload.argtypes = [vp]
         L.ec_batch_reserve.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
@@ -103,7 +106,7 @@ def lib():
         L.ec_batch_free.argtypes = [vp]
         L.ec_batch_free.restype = None
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
-                     "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_batch_build", "ec_device_copy",
+                     "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_program_part_bytecode", "ec_batch_build", "ec_device_copy",
                      "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set"):
             getattr(L, name).restype = st
         _lib = L
@@ -237,14 +240,22 @@ class Program:
         _check(lib().ec_program_bytecode(self._h, ctypes.byref(w), ctypes.byref(n)), "ec_program_bytecode")
         return [w[i] for i in range(n.value)]
 
+    def part_bytecode(self, part: int):
+        """Words of row-split part ``part`` (0 <= part < info["n_parts"])."""
+        w = ctypes.POINTER(ctypes.c_uint32)()
+        n = ctypes.c_size_t()
+        _check(lib().ec_program_part_bytecode(self._h, part, ctypes.byref(w), ctypes.byref(n)),
+               "ec_program_part_bytecode")
+        return [w[i] for i in range(n.value)]
+
 
 def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
                    compress: int = COMPRESS_XORREPAIR, block_strips: int = 0,
-                   prefetch: int | None = None) -> Program:
+                   prefetch: int | None = None, split: int = SPLIT_AUTO) -> Program:
     er = list(erased)
     er_arr = (ctypes.c_int * max(1, len(er)))(*er)
     opts = CompileOpts(level, slot_budget, compress, block_strips,
-                       DEFAULT_PREFETCH if prefetch is None else prefetch)
+                       DEFAULT_PREFETCH if prefetch is None else prefetch, split)
     h = ctypes.c_void_p()
     _check(lib().ec_compile_slp(n, p, _flat_gen(gen, n, p), er_arr, len(er), ctypes.byref(opts), ctypes.byref(h)),
            "ec_compile_slp")

@@ -103,12 +103,28 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   if (a.strip_len % (4u << 20) == 0 && a.n_tiles % 8 == 0) a.seg_shift = 3;
   a.seg_mask = (1u << a.seg_shift) - 1;
   a.seg_tiles = a.n_tiles >> a.seg_shift;
-  // As many workgroups as stay resident (4 waves each, one per SIMD, times
-  // the waves per SIMD the slot budget allows), each looping over tiles:
-  // measured 3-6% faster than one workgroup per 4 tiles.
   const int n_cus = device_cus();
   if (n_cus <= 0) return EC_ERR_DEVICE;
-  const int grid = (int)std::min<uint64_t>((a.n_tiles + 3) / 4, (uint64_t)n_cus * waves_per_simd(prog->slots));
+  const uint64_t resident = (uint64_t)n_cus * waves_per_simd(prog->slots);  // workgroups of 4 waves
+  // Row split for short stripes: when one wave per (tile, part) still fits
+  // in one round of resident waves.  Measured on RS(10,4) encodes, 4 parts:
+  // 30-31 us -> 23 us per launch for blocks up to 2 MiB (256 tiles),
+  // 31.0 -> 28.4 us at 4 MiB, but 32 -> 47 us at 8 MiB (the parts re-read
+  // the inputs, and past one round those reads go to HBM again).
+  a.n_parts = 1;
+  a.part_off[0] = 0;
+  const uint64_t parts = prog->parts.size();
+  const bool split = parts > 0 && (prog->split == EC_SPLIT_ALWAYS ||
+                                   (prog->split == EC_SPLIT_AUTO && (uint64_t)a.n_tiles * parts <= 4 * resident));
+  if (split) {
+    a.n_parts = (uint32_t)prog->parts.size();
+    for (uint32_t q = 0; q < a.n_parts; ++q) a.part_off[q] = prog->part_off[q];
+  }
+  // As many workgroups as stay resident (4 waves each, one per SIMD, times
+  // the waves per SIMD the slot budget allows), each looping over its work
+  // items: measured 3-6% faster than one workgroup per 4 tiles.
+  const uint64_t n_work = (uint64_t)a.n_tiles * a.n_parts;
+  const int grid = (int)std::min<uint64_t>((n_work + 3) / 4, resident);
   if (exec_launch(prog->slots, a, grid, (hipStream_t)stream) != 0) return EC_ERR_DEVICE;
   return EC_OK;
 }
@@ -153,6 +169,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
+  if (o.split > EC_SPLIT_ALWAYS) return EC_ERR_UNSUPPORTED;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -249,6 +266,34 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   prog->slots = po.slots;
   if (!simulate_code(prog->code.words, prog->slots, n_in, n_out, brows)) return EC_ERR_UNSUPPORTED;
 
+  // Row-split parts: groups of whole output blocks, each scheduled alone on
+  // the same slot budget (so with a deeper load ring); checked like the
+  // whole program, and dropped if any group does not fit in one pass.
+  prog->split = (int)o.split;
+  prog->image = prog->code.words;
+  prog->part_off.clear();
+  if (n_out > 1 && o.split != EC_SPLIT_NEVER) {
+    const int groups = std::min(n_out, kMaxParts);
+    for (int g = 0; g < groups; ++g) {
+      PushOpts pp = po;
+      pp.row_lo = 8 * (g * n_out / groups);
+      pp.row_hi = 8 * ((g + 1) * n_out / groups);
+      pp.max_ring = 24;
+      PushCode part;
+      if (push_schedule(dag, n_in, pp, part) != 0 || part.passes != 1) {
+        prog->parts.clear();
+        break;
+      }
+      if (!simulate_code(part.words, prog->slots, n_in, n_out, brows, pp.row_lo, pp.row_hi))
+        return EC_ERR_UNSUPPORTED;
+      prog->parts.push_back(std::move(part));
+    }
+    for (const PushCode &part : prog->parts) {
+      prog->part_off.push_back((uint32_t)prog->image.size());
+      prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
+    }
+  }
+
   ec_program_info &info = prog->info;
   info.n = (uint32_t)n;
   info.p = (uint32_t)p;
@@ -269,6 +314,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_records = (uint32_t)prog->code.n_records;
   info.n_ops = (uint32_t)prog->code.n_ops;
   info.n_words = (uint32_t)prog->code.words.size();
+  info.n_parts = (uint32_t)prog->parts.size();
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -356,6 +402,13 @@ ec_status ec_program_upload(ec_program *prog) {
   if (!prog) return EC_ERR_ARG;
   ec_status st = EC_OK;
   return prog->device_words(&st) ? EC_OK : st;
+}
+
+ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words) {
+  if (!prog || !words || !n_words || part < 0 || part >= (int)prog->parts.size()) return EC_ERR_ARG;
+  *words = prog->parts[part].words.data();
+  *n_words = prog->parts[part].words.size();
+  return EC_OK;
 }
 
 ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, size_t *n_words) {

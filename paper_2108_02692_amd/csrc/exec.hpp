@@ -8,6 +8,7 @@ namespace ec {
 
 constexpr int kMaxBlocks = 32;  // input + output blocks of one stripe
 constexpr int kTileBytes = 1024;  // bytes of each strip per wave (64 lanes x 16 B)
+constexpr int kMaxParts = 8;      // row-split parts of one program
 
 // Kernel arguments of a single-stripe launch (passed by value).
 struct ExecArgs {
@@ -20,6 +21,11 @@ struct ExecArgs {
   // consecutive waves take tiles in 1 << seg_shift distant segments of the
   // strips (identity when seg_shift = 0).
   uint32_t seg_shift, seg_mask, seg_tiles;
+  // Row split: work item k runs part k % n_parts (the program at word
+  // part_off[k % n_parts] of prog) on tile k / n_parts; n_parts = 1 and
+  // part_off[0] = 0 run the whole program on every tile.
+  uint32_t n_parts;
+  uint32_t part_off[kMaxParts];
 };
 
 // One stripe of a batched launch (device memory, read-only during a launch).

@@ -212,11 +212,11 @@ typedef const __attribute__((address_space(4))) uint32_t *ConstU32Ptr;
 
 PER_K = r'''// ---- %(K)d slots
 #define EC_INIT_%(K)d asm volatile(%(INIT)s : %(OUT)s)
-#define EC_RUN_%(K)d(prog, voff, tlo, thi, sl)  \
+#define EC_RUN_%(K)d(prog_, voff_, tlo_, thi_, sl_)  \
   asm volatile(                                  \
 %(PROGRAM)s
       : %(INOUT)s                                \
-      : [prog] "s"(prog), [voff] "v"(voff), [tlo] "v"(tlo), [thi] "v"(thi), [sl] "s"(sl) \
+      : [prog] "s"(prog_), [voff] "v"(voff_), [tlo] "v"(tlo_), [thi] "v"(thi_), [sl] "s"(sl_) \
       : %(CLOB)s)
 
 __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
@@ -234,12 +234,22 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
   const uint32_t *prog = a.prog;
   %(DECLS)s
   EC_INIT_%(K)d;
-  for (uint32_t k = wave; k < a.n_tiles; k += n_waves) {
-    const uint32_t tile = (k & a.seg_mask) * a.seg_tiles + (k >> a.seg_shift);
+  // work item k: part k %% n_parts of tile k / n_parts (the whole program
+  // on tile k when n_parts = 1)
+  const uint32_t n_parts = a.n_parts;
+  const uint32_t n_work = a.n_tiles * n_parts;
+  for (uint32_t k = wave; k < n_work; k += n_waves) {
+    uint32_t kt = k;
+    const uint32_t *pk = prog;
+    if (n_parts > 1) {
+      kt = k / n_parts;
+      pk = prog + a.part_off[k - kt * n_parts];
+    }
+    const uint32_t tile = (kt & a.seg_mask) * a.seg_tiles + (kt >> a.seg_shift);
     const uint64_t toff = (uint64_t)tile * kTileBytes;
     const uint64_t t = tile_table(tab, toff);
     const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-    if (toff + voff < sl) EC_RUN_%(K)d(prog, voff, tlo, thi, sl);
+    if (toff + voff < sl) EC_RUN_%(K)d(pk, voff, tlo, thi, sl);
   }
 }
 

@@ -25,6 +25,10 @@ struct ec_program {
   bool stages_built = false;
   ec::Slp exec;                  // the push-form program the executor runs, as an SLP
   ec::PushCode code;
+  std::vector<ec::PushCode> parts;  // row-split parts (empty: none)
+  std::vector<uint32_t> image;      // device image: code.words, then every part's words
+  std::vector<uint32_t> part_off;   // word offset of each part in the image
+  int split = EC_SPLIT_AUTO;
   ec_program_info info{};
   std::mutex mu;
   std::map<int, uint32_t *> dev_words;  // device -> bytecode copy
@@ -58,9 +62,9 @@ struct ec_program {
     auto it = dev_words.find(dev);
     if (it != dev_words.end()) return it->second;
     uint32_t *d = nullptr;
-    const size_t bytes = code.words.size() * sizeof(uint32_t);
+    const size_t bytes = image.size() * sizeof(uint32_t);
     if (hipMalloc((void **)&d, bytes) != hipSuccess) { *st = EC_ERR_NOMEM; return nullptr; }
-    if (hipMemcpy(d, code.words.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(d, image.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipFree(d);
       *st = EC_ERR_DEVICE;
       return nullptr;

@@ -503,11 +503,13 @@ int peak_open_temps(const PushDag &d) {
 }  // namespace
 
 int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushCode &out) {
-  const int K = opts.slots, R = d.n_rows;
+  const int K = opts.slots;
+  const int R = opts.row_hi < 0 ? d.n_rows : std::min(opts.row_hi, d.n_rows);
+  if (opts.row_lo < 0 || opts.row_lo % 8 || (opts.row_lo >= R && R > 0)) return -1;
   // Passes: as many whole output blocks per pass as fit beside the pass's
   // open temporaries and a ring of at least two strips.
   std::vector<Pass> passes;
-  for (int r0 = 0; r0 < R;) {
+  for (int r0 = opts.row_lo; r0 < R;) {
     int take = 0;
     for (int nb = (R - r0 + 7) / 8; nb >= 1; --nb) {
       const int cnt = std::min(8 * nb, R - r0);
@@ -622,7 +624,8 @@ bool validate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
 }
 
 bool simulate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, int n_out_blocks,
-                   const std::vector<Bits> &rows) {
+                   const std::vector<Bits> &rows, int row_lo, int row_hi) {
+  if (row_hi < 0) row_hi = (int)rows.size();
   if (!validate_code(w, slots, n_in_blocks, n_out_blocks)) return false;
   std::vector<Bits> slot(slots);
   std::vector<char> busy(slots, 0);     // a load into the slot is in flight
@@ -672,8 +675,10 @@ bool simulate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
       }
       pc += 2 + n;
     }
-    for (size_t r = 0; r < rows.size(); ++r)
-      if (!written[r] || !(out[r] == rows[r])) return false;
+    for (int r = 0; r < (int)written.size(); ++r) {
+      const bool want = r >= row_lo && r < row_hi && r < (int)rows.size();
+      if (want != (bool)written[r] || (want && !(out[r] == rows[r]))) return false;
+    }
     for (int s = 0; s < slots; ++s)
       if (busy[s] || !(slot[s] == Bits())) return false;  // loads consumed, slots left zero
   }

@@ -62,6 +62,8 @@ struct PushOpts {
   int slots = 40;     // register slots (16 B per lane each)
   int max_ring = 12;  // most input strips loaded ahead of their use
   int prefetch = 0;   // strips touched this far ahead of their register load (0 = none)
+  int row_lo = 0;     // rows scheduled: [row_lo, row_hi), whole output blocks
+  int row_hi = -1;    // (-1: every row)
 };
 
 struct PushCode {
@@ -94,7 +96,9 @@ bool validate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, i
 // read before its load has been waited for, that no load lands in a slot
 // that is still being read or accumulated, and that every slot is zero again
 // at the end of a tile.
+// With row_lo / row_hi, only rows [row_lo, row_hi) are expected, and a
+// store of any other row is an error.
 bool simulate_code(const std::vector<uint32_t> &w, int slots, int n_in_blocks, int n_out_blocks,
-                   const std::vector<Bits> &rows);
+                   const std::vector<Bits> &rows, int row_lo = 0, int row_hi = -1);
 
 }  // namespace ec

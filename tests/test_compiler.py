@@ -260,3 +260,30 @@ def test_compile_errors():
     with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
     assert e.value.name == "EC_ERR_ARG"
+
+
+@pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, (1, 7)), (14, 4, (0, 13)),
+                                    (28, 4, ()), (4, 12, ()), (10, 2, (8, 9))])
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
+def test_row_split_parts_cover_the_rows(n, p, er, level):
+    """Every row-split part, run by the independent simulator, stores only its
+    own output blocks; together they store every output strip with the
+    bitmatrix row's value, exactly once."""
+    gen = E.ec_matrix_cauchy(n, p)
+    rows = oracle_rows(gen, n, p, er)
+    prog = E.ec_compile_slp(n, p, gen, er, level=level)
+    n_out = len(prog.out_blocks)
+    n_parts = prog.info["n_parts"]
+    assert n_parts == (min(n_out, 8) if n_out > 1 else 0) or n_parts == 0
+    got = {}
+    for q in range(n_parts):
+        part = simulate(prog.part_bytecode(q), prog.info["slots"], len(prog.in_blocks), n_out)
+        assert part and not set(part) & set(got)
+        # a part holds whole output blocks
+        assert all(8 * (o // 8) + j in part for o in part for j in range(8))
+        got.update(part)
+    if n_parts:
+        assert [got[o] for o in range(len(rows))] == rows
+    assert E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_NEVER).info["n_parts"] == 0
+    with pytest.raises(E.EcError):
+        prog.part_bytecode(n_parts)
