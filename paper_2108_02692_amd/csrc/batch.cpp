@@ -145,6 +145,7 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   std::vector<std::pair<uintptr_t, uintptr_t>> reads, writes;
   int slots = 0;
   size_t in_bytes = 0, out_bytes = 0;
+  uint64_t tiles_split = 0;  // work items of the batch with the row split
   for (int s = 0; s < n_stripes; ++s) {
     const ec_stripe &st = stripes[s];
     const ec_program *prog = st.prog;
@@ -172,6 +173,23 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     if (!d.prog) return ws;
     d.n_blocks = (uint32_t)(n_in + n_out);
     d.strip_len = (uint32_t)(st.block_bytes / 8);
+    const uint64_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
+    tiles_split += n_tiles * std::max<size_t>(1, prog->parts.size());
+    in_bytes += (size_t)n_in * st.block_bytes;
+    out_bytes += (size_t)n_out * st.block_bytes;
+  }
+  // Row split (the programs' parts) when one wave per (tile, part) of the
+  // whole batch fits in one round of resident waves, as for one stripe.
+  const uint64_t resident_waves = 4ull * (uint64_t)b->n_cus * waves_per_simd(slots);
+  const bool fits = tiles_split <= resident_waves;
+  for (int s = 0; s < n_stripes; ++s) {
+    const ec_program *prog = stripes[s].prog;
+    StripeDesc &d = desc[s];
+    const bool split = !prog->parts.empty() &&
+                       (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && fits));
+    const uint32_t n_parts = split ? (uint32_t)prog->parts.size() : 1u;
+    for (uint32_t q = 0; q < (uint32_t)kMaxParts; ++q)
+      d.part_off[q] = split && q < n_parts ? prog->part_off[q] : 0u;
     const uint32_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
     const uint32_t n_its = (n_tiles + tiles_per_item - 1) / tiles_per_item;
     // Strips a multiple of 4 MiB apart: consecutive items from 8 distant
@@ -179,11 +197,11 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     const bool spread = d.strip_len % (4u << 20) == 0 && n_its % 8 == 0;
     for (uint32_t k = 0; k < n_its; ++k) {
       const uint32_t i = spread ? (k & 7u) * (n_its >> 3) + (k >> 3) : k;
-      items.push_back((uint32_t)s);
-      items.push_back(i * tiles_per_item);
+      for (uint32_t q = 0; q < n_parts; ++q) {  // a tile's parts side by side
+        items.push_back((uint32_t)s);
+        items.push_back(i * tiles_per_item | q << kItemPartShift);
+      }
     }
-    in_bytes += (size_t)n_in * st.block_bytes;
-    out_bytes += (size_t)n_out * st.block_bytes;
   }
   if (items.size() / 2 > 0xFFFFFFFFull) return EC_ERR_UNSUPPORTED;
   if (!disjoint_writes(reads, writes)) return EC_ERR_ARG;

@@ -30,16 +30,21 @@ struct ExecArgs {
 
 // One stripe of a batched launch (device memory, read-only during a launch).
 struct StripeDesc {
-  uint64_t blk[kMaxBlocks];  // input block pointers, then output block pointers
-  const uint32_t *prog;      // the stripe's device bytecode
-  uint32_t n_blocks;         // input + output blocks
-  uint32_t strip_len;        // bytes per strip
-};
+  uint64_t blk[kMaxBlocks];      // input block pointers, then output block pointers
+  const uint32_t *prog;          // the stripe's device image
+  uint32_t n_blocks;             // input + output blocks
+  uint32_t strip_len;            // bytes per strip
+  uint32_t part_off[kMaxParts];  // word offset in prog of each part a work item may name
+};                               // (part 0 at offset 0: the whole program, when not split)
+
+// Second word of a work item: first tile in the low bits, part above.
+constexpr uint32_t kItemPartShift = 24;
+constexpr uint32_t kItemTileMask = (1u << kItemPartShift) - 1;
 
 // Arguments of the persistent batched kernel.
 struct BatchArgs {
   const StripeDesc *stripes;
-  const uint32_t *items;  // 2 words per work item: stripe index, tile index
+  const uint32_t *items;  // 2 words per work item: stripe index, tile | part << kItemPartShift
   uint32_t n_items;
   uint32_t tiles_per_item;  // consecutive tiles one work item covers
   uint32_t chunk;           // items taken per atomic add on the counter

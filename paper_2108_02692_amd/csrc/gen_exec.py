@@ -272,9 +272,10 @@ __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
     const uint32_t last = min(first + a.chunk, a.n_items);
     for (uint32_t it = first; it < last; ++it) {
       const uint32_t stripe = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it];
-      const uint32_t tile = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it + 1];
+      const uint32_t word = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it + 1];
+      const uint32_t tile = word & kItemTileMask, part = word >> kItemPartShift;
       ConstDescPtr d = (ConstDescPtr)(uintptr_t)(a.stripes + stripe);
-      const uint32_t *prog = d->prog;
+      const uint32_t *prog = d->prog + d->part_off[part];
       const uint32_t sl = d->strip_len;
       if (stripe != cur) {
         // lane b <- pointer of block b, written lane by lane from scalar

@@ -99,7 +99,8 @@ def test_reusable_batch_reserve_and_refill():
     batch.free()
 
 
-def test_batch_edge_shapes_and_mixed_levels():
+@pytest.mark.parametrize("split", [E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS])
+def test_batch_edge_shapes_and_mixed_levels(split):
     """One batch holding the extremes: the widest codec (32 blocks), 1-block
     codecs, blocks of 128 B (one lane of one tile per strip) and ragged
     sizes, encodes and decodes, programs of different levels at one slot
@@ -112,7 +113,8 @@ def test_batch_edge_shapes_and_mixed_levels():
         gen = E.ec_matrix_cauchy(n, p)
         G = np.array(gen, dtype=np.uint8)
         level = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU_SCHED)[k % 3]
-        prog = E.ec_compile_slp(n, p, gen, list(er), level=level, slot_budget=44)
+        prog = E.ec_compile_slp(n, p, gen, list(er), level=level, slot_budget=44,
+                                split=split if k % 2 else E.SPLIT_AUTO)
         data = [rng.integers(0, 256, S, dtype=np.uint8) for _ in range(n)]
         blocks = data + oracle.encode(G, n, p, data)
         if er:
