@@ -82,9 +82,13 @@ def time_launches(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps
 
 
-def sha256_file(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def code_sha(path):
+    """sha256 of a C++/HIP source with comments and blank lines removed, so
+    that an edit of comments alone keeps a measurement valid."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()
 
 
 def program_sha(prog):
@@ -97,7 +101,7 @@ def measured_traffic(prog):
     """HBM bytes per launch from the committed byte-counter profile of this
     workload, if it was taken on this executor and this program (else None)."""
     import paper_2108_02692_amd
-    exec_sha = sha256_file(os.path.join(os.path.dirname(paper_2108_02692_amd.__file__), "csrc", "exec.hip"))
+    exec_sha = code_sha(os.path.join(os.path.dirname(paper_2108_02692_amd.__file__), "csrc", "exec.hip"))
     psha = program_sha(prog)
     if not os.path.isdir(PROFILES):
         return None
@@ -107,7 +111,7 @@ def measured_traffic(prog):
         with open(os.path.join(PROFILES, name)) as f:
             for m in re.finditer(r"<!-- traffic (\{.*?\}) -->", f.read()):
                 rec = json.loads(m.group(1))
-                if rec.get("exec_hip_sha256") == exec_sha and rec.get("program_sha256") == psha:
+                if rec.get("exec_hip_code_sha256") == exec_sha and rec.get("program_sha256") == psha:
                     return rec["fetch_bytes"] + rec["write_bytes"]
     return None
 

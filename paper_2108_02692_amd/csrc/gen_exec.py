@@ -157,9 +157,9 @@ def program_asm(K):
 HEAD = r'''// exec.hip -- gfx950 executor for push-form XOR programs.
 // GENERATED by gen_exec.py -- edit that file and regenerate.
 //
-// One wave runs the whole program on one tile: 64 lanes x 16 bytes = 1 KiB
-// of every input and output strip (the blocked loop of Sec. 6.1; the tile is
-// the paper's block size).  The accumulator is pinned to v[0:3] and K
+// One wave runs the whole program, or one row-split part of it, on one tile:
+// 64 lanes x 16 bytes = 1 KiB of every input and output strip (the blocked
+// loop of Sec. 6.1; the tile is the paper's block size).  The accumulator is pinned to v[0:3] and K
 // register slots of 16 bytes per lane to v[4 : 4+4K).  The program is a
 // stream of records (bytecode.hpp) read through the scalar cache, two
 // 16-word windows in turn, the next record's window loading while the
