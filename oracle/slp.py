@@ -445,9 +445,21 @@ def iocost(stmts, capacity: int) -> int:
 
 
 def ccap(stmts) -> int:
-    """CCap (Sec. 6.2): the least capacity that runs without reloading."""
-    need = max(len(ops) + 1 for _, ops in stmts)
-    c = need
-    while lru_run(stmts, c)[2] != 0:
-        c += 1
-    return c
+    """CCap (Sec. 6.2): the least capacity that runs without reloading.
+
+    LRU has the inclusion property (what a cache of c entries holds at any
+    moment, one of c + 1 entries holds too), so a program that runs without
+    reloading at capacity c does so at every larger capacity and the least
+    such capacity can be found by bisection.  It is at least the largest
+    statement's arity + 1."""
+    lo = max(len(ops) + 1 for _, ops in stmts)
+    hi = lo
+    while lru_run(stmts, hi)[2] != 0:
+        hi *= 2
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if lru_run(stmts, mid)[2] != 0:
+            lo = mid + 1
+        else:
+            hi = mid
+    return lo

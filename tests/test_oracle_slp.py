@@ -325,3 +325,16 @@ def test_paper_schedule_measures_approx(paper_enc_rows, paper_dec_rows):
             assert S.evaluate(g, ret, 80, isc) == S.evaluate(fused, outs, 80, comp.is_const)
             assert within(gn, about["nvar"], tol["about_nvar"]), (b, gn)
             assert within(S.ccap(g), about["ccap"], tol["about_ccap"]), (b, S.ccap(g))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ccap_bisection_equals_the_least_capacity(seed):
+    # CCap searched by bisection (LRU inclusion) equals the first capacity
+    # found by trying every capacity upward
+    rng = random.Random(100 + seed)
+    stmts, _ = random_program(rng, 16, 40)
+    c = max(len(ops) + 1 for _, ops in stmts)
+    while S.lru_run(stmts, c)[2]:
+        c += 1
+    assert S.ccap(stmts) == c
+    assert S.lru_run(stmts, c - 1)[2] > 0 or c == max(len(ops) + 1 for _, ops in stmts)

@@ -110,3 +110,50 @@ def test_codec_figure_measures(codec):
         assert [(v, [term(o) for o in ops]) for v, ops in pfu] == fu and [term(o) for o in pouts] == outs
         psched, _ = prog.export(E.STAGE_SCHED)
         assert [(v, [term(o) for o in ops]) for v, ops in psched] == order
+
+
+# ---- Sec. 7.3: average NVar and CCap ratios
+def _nvar_ccap(rows):
+    """NVar and CCap of P, Co(P), Fu(P), Fu(Co(P)) and Dfs(Fu(Co(P))) for one
+    program: the stages are the library's (equal to the oracle's, see
+    test_compiler.py), the measures the oracle's LRU model."""
+    from oracle import slp as S
+    big = S.Compressed.BIG
+    term = lambda x: S.ZERO if x == -1 else (big + (-x - 2) if x <= -2 else x)
+    conv = lambda st: [(v, [term(o) for o in ops]) for v, ops in st]
+    isc = lambda t: isinstance(t, int) and t >= big
+    n, k = 10, len(rows)
+    gen = np.vstack([np.eye(n, dtype=np.uint8), rows]).tolist()
+    prog = E.ec_compile_slp(n, k, gen)
+    plain = conv(prog.export(E.STAGE_PLAIN)[0])
+    chain = []  # P: each row accumulated in its own variable by binary XORs
+    for v, ops in plain:
+        chain.append((v, ops[:2]))
+        chain += [(v, [v, o]) for o in ops[2:]]
+    co = conv(prog.export(E.STAGE_CO)[0])
+    fu, fouts = prog.export(E.STAGE_FU)
+    fu = conv(fu)
+    fouts = [term(o) for o in fouts]
+    peb, _, npeb = S.assign_pebbles(conv(prog.export(E.STAGE_SCHED)[0]), fouts, isc)
+    nv_p, nv_co = S.nvar(chain), S.nvar(co)
+    cc_p, cc_co = S.ccap(chain), S.ccap(co)
+    return (nv_co / nv_p, S.nvar(plain) / nv_p, S.nvar(fu) / nv_co, npeb / nv_co,
+            cc_co / cc_p, S.ccap(plain) / cc_p, S.ccap(fu) / cc_co, S.ccap(peb) / cc_co)
+
+
+@pytest.mark.slow
+def test_average_nvar_ccap_ratios_match_printed():
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    ref = json.load(open(GOLDEN))
+    progs = programs()
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("fork")) as ex:
+        res = np.array(list(ex.map(_nvar_ccap, progs, chunksize=8)))
+    avg = res.mean(axis=0)
+    keys = ("co_over_p", "fu_over_p", "fuco_over_co", "dfs_over_co")
+    tol = ref["tolerance_rel_nvar_ccap"]
+    for i, k in enumerate(keys):
+        for table, got in (("nvar_ratio", avg[i]), ("ccap_ratio", avg[4 + i])):
+            want = ref[table][k]
+            assert abs(got - want) <= tol * want, (table, k, got, want)
