@@ -109,8 +109,8 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   // Row split for short stripes: when one wave per (tile, part) still fits
   // in one round of resident waves.  Measured on RS(10,4) encodes, 4 parts:
   // 30-31 us -> 23 us per launch for blocks up to 2 MiB (256 tiles),
-  // 31.0 -> 28.4 us at 4 MiB, but 32 -> 47 us at 8 MiB (the parts re-read
-  // the inputs, and past one round those reads go to HBM again).
+  // 31.0 -> 28.4 us at 4 MiB, but 32 -> 47 us at 8 MiB: every part reads
+  // every input, so once the waves are busy anyway the split only adds work.
   a.n_parts = 1;
   a.part_off[0] = 0;
   const uint64_t parts = prog->parts.size();
