@@ -343,3 +343,38 @@ def test_row_split_matches_oracle(n, p, er):
             prog = E.ec_compile_slp(n, p, gen, list(er), split=split)
             got = run_decode(prog, blocks, S) if er else run_encode(prog, data, S)
             assert_blocks_equal(got, want, "RS(%d,%d) %s S=%d split %d" % (n, p, er, S, split))
+
+
+def test_random_cases_match_oracle():
+    """Seeded random cases over the whole compile space: codec (up to 32
+    blocks), erasure set, level, slot budget, split policy and block size
+    (any multiple of 128 B up to 384 KiB), each compared with the oracle."""
+    rng = random.Random(2024)
+    budgets = (0, 24, 32, 36, 38, 40, 44, 48)
+    levels = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED)
+    splits = (E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS)
+    done = 0
+    while done < 40:
+        n = rng.randint(1, 20)
+        p = rng.randint(0, min(8, 32 - n))
+        k = rng.randint(0, p)
+        er = tuple(sorted(rng.sample(range(n + p), k)))
+        S = 128 * rng.randint(1, 3072)
+        gen = E.ec_matrix_cauchy(n, p)
+        try:
+            prog = E.ec_compile_slp(n, p, gen, list(er), level=rng.choice(levels),
+                                    slot_budget=rng.choice(budgets), split=rng.choice(splits))
+        except E.EcError as e:  # a budget too small for the codec
+            assert e.name == "EC_ERR_CAPACITY", e
+            continue
+        if not prog.out_blocks:
+            continue
+        G = np.array(gen, dtype=np.uint8)
+        data = W.host_blocks(n, S, seed=rng.randint(0, 1 << 30))
+        blocks = data + oracle.encode(G, n, p, data) if p else data
+        what = "RS(%d,%d) %s S=%d %s" % (n, p, er, S, prog.info)
+        if er:
+            assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], what)
+        else:
+            assert_blocks_equal(run_encode(prog, data, S), blocks[n:], what)
+        done += 1
