@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import LEVEL_CO_FU_SCHED, Batch
+from . import LEVEL_CO_FU_SCHED, Batch, ec_decode, ec_encode
 from .batching import ProgramCache
 
 MAX_OBJECT = 64 << 20  # largest object served (bytes)
@@ -90,13 +90,14 @@ class Server:
     stream with a reusable ``ec_batch``."""
 
     def __init__(self, budget_bytes=16 << 30, n_slots=4, max_batch=512, level=LEVEL_CO_FU_SCHED, slots=38,
-                 tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True):
+                 tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True, direct_single=True):
         import torch
         self.torch = torch
         self.budget = budget_bytes
         self.used = 0
         self.max_batch = max_batch
         self.tile_bytes = tile_bytes
+        self.direct_single = direct_single
         self.cache = ProgramCache(level=level, slots=slots)
         if warm:
             self.cache.warm([(n, p, er) for n, p in codecs for er in self.cache.all_patterns(n, p)])
@@ -136,9 +137,17 @@ class Server:
         return None
 
     def launch(self, slot, reqs):
-        stripes = [(self.cache.get(r.n, r.p, r.erased), r.inputs, r.outputs, r.block_bytes) for r in reqs]
-        slot["batch"].set(stripes, tile_bytes=self.tile_bytes, stream=slot["stream"])
-        slot["batch"].enqueue(slot["stream"])
+        if len(reqs) == 1 and self.direct_single:
+            # one request: a plain launch, without the batch's tables and
+            # work counter (measured: 38 us from call to completion against
+            # 58 us through a batch, for 26 KiB blocks)
+            r = reqs[0]
+            prog = self.cache.get(r.n, r.p, r.erased)
+            (ec_decode if r.erased else ec_encode)(prog, r.inputs, r.outputs, r.block_bytes, slot["stream"])
+        else:
+            stripes = [(self.cache.get(r.n, r.p, r.erased), r.inputs, r.outputs, r.block_bytes) for r in reqs]
+            slot["batch"].set(stripes, tile_bytes=self.tile_bytes, stream=slot["stream"])
+            slot["batch"].enqueue(slot["stream"])
         slot["event"].record(slot["stream"])
         slot["reqs"] = reqs
         self.batches += 1
