@@ -116,6 +116,23 @@ class Server:
             self.slots.append({"stream": torch.cuda.Stream(), "batch": b, "event": torch.cuda.Event(),
                                "reqs": None})
         self.batches = 0
+        self._warm(codecs)
+
+    def _warm(self, codecs):
+        """One tiny encode per codec on every slot's stream, directly and as
+        a batch, before any request: the first launches on a new stream (and
+        of each kernel) take milliseconds, which the first requests would
+        otherwise wait for.  Blocks of 128 B at the start of the (still
+        empty) arena serve as inputs and outputs."""
+        for n, p in codecs:
+            prog = self.cache.get(n, p, ())
+            ins = [self.base + 128 * i for i in range(n)]
+            outs = [self.base + 128 * (n + j) for j in range(p)]
+            for s in self.slots:
+                ec_encode(prog, ins, outs, 128, s["stream"])
+                s["batch"].set([(prog, ins, outs, 128)], tile_bytes=self.tile_bytes, stream=s["stream"])
+                s["batch"].enqueue(s["stream"])
+        self.torch.cuda.synchronize()
 
     def try_admit(self, req: Request) -> bool:
         out_bytes = req.n_out * req.block_bytes
