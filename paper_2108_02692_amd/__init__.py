@@ -59,8 +59,10 @@ class ProgramInfo(ctypes.Structure):
 
 
 class Stripe(ctypes.Structure):
-    _fields_ = [("prog", ctypes.c_void_p), ("in_", ctypes.POINTER(ctypes.c_void_p)),
-                ("out", ctypes.POINTER(ctypes.c_void_p)), ("block_bytes", ctypes.c_size_t)]
+    # in_ / out are `const uint8_t *const *` in C; held as plain addresses
+    # (same layout) so that they can point into one array per batch
+    _fields_ = [("prog", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("block_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -155,10 +157,7 @@ def _ptr(x) -> int:
 
 
 def _ptr_array(xs):
-    arr = (ctypes.c_void_p * max(1, len(xs)))()
-    for i, x in enumerate(xs):
-        arr[i] = _ptr(x)
-    return arr
+    return (ctypes.c_void_p * max(1, len(xs)))(*[x if type(x) is int else _ptr(x) for x in xs])
 
 
 def _stream_handle(stream) -> int | None:
@@ -304,8 +303,8 @@ class Batch:
     def set(self, stripes, tile_bytes: int = 0, stream=None):
         """Refill with ``stripes`` ((Program, inputs, outputs, block_bytes));
         asynchronous on ``stream``; the previous launch must have finished."""
-        arr, keep = _stripe_array(stripes)
-        _check(lib().ec_batch_set(self._h, arr, len(keep) // 3, tile_bytes, _stream_handle(stream)),
+        arr, keep, n = _stripe_array(stripes)
+        _check(lib().ec_batch_set(self._h, arr, n, tile_bytes, _stream_handle(stream)),
                "ec_batch_set")
         self._keep = keep
         self._query()
@@ -335,24 +334,32 @@ class Batch:
 
 
 def _stripe_array(stripes):
+    """(ctypes array of Stripe, objects to keep alive, number of stripes):
+    every stripe's block pointers in one flat array."""
     stripes = list(stripes)
     arr = (Stripe * max(1, len(stripes)))()
-    keep = []
+    flat = [p if type(p) is int else _ptr(p) for _, ins, outs, _ in stripes for p in (*ins, *outs)]
+    ptrs = (ctypes.c_void_p * max(1, len(flat)))(*flat)
+    base, step = ctypes.addressof(ptrs), ctypes.sizeof(ctypes.c_void_p)
+    keep = [ptrs]
+    k = 0
     for i, (prog, ins, outs, bb) in enumerate(stripes):
-        ia, oa = _ptr_array(ins), _ptr_array(outs)
-        keep += [prog, ia, oa]
-        arr[i].prog = prog.handle.value
-        arr[i].in_ = ctypes.cast(ia, ctypes.POINTER(ctypes.c_void_p))
-        arr[i].out = ctypes.cast(oa, ctypes.POINTER(ctypes.c_void_p))
-        arr[i].block_bytes = bb
-    return arr, keep
+        keep.append(prog)
+        s = arr[i]
+        s.prog = prog.handle.value
+        s.in_ = base + step * k
+        k += len(ins)
+        s.out = base + step * k
+        k += len(outs)
+        s.block_bytes = bb
+    return arr, keep, len(stripes)
 
 
 def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
     """``stripes``: iterable of (Program, inputs, outputs, block_bytes).
     Uploads the tables (waiting on ``stream``) and captures a HIP graph."""
-    arr, keep = _stripe_array(stripes)
+    arr, keep, n = _stripe_array(stripes)
     h = ctypes.c_void_p()
-    _check(lib().ec_batch_build(arr, len(keep) // 3, tile_bytes, _stream_handle(stream), ctypes.byref(h)),
+    _check(lib().ec_batch_build(arr, n, tile_bytes, _stream_handle(stream), ctypes.byref(h)),
            "ec_batch_build")
     return Batch(h.value, keep)
