@@ -84,21 +84,30 @@ typedef struct {
   uint32_t prefetch;     /* distance in strips at which strips are touched (4 B per lane)
                             ahead of their register load, so that the load finds them in
                             the L2 cache; 0 = none (NULL opts: the library's default) */
-  uint32_t split;        /* EC_SPLIT_*: whether a launch may run the output blocks of one
+  uint32_t split;        /* EC_SPLIT_*: whether a launch may run the output rows of one
                             tile on different waves (see ec_program_info.n_parts) */
 } ec_compile_opts;
 
-/* Row split.  A program with more than one output block also carries
- * "parts": up to 8 independent programs, each computing a group of whole
- * output blocks from all the inputs.  A launch over a stripe with few tiles
- * then runs one wave per (tile, part) instead of one per tile, which gives
- * short stripes more waves and each wave a deeper load ring, at the cost of
- * reading each input once per part (mostly from the caches). */
+/* Row split.  Unless compiled with EC_SPLIT_NEVER, a program also carries
+ * "parts": independent programs that each compute some of the output rows
+ * from the inputs they need, in two sets:
+ *  - block parts: up to 8, each a group of whole output blocks (only when
+ *    there is more than one output block);
+ *  - row parts: up to 32, each one bit row (groups of ceil(8 n_out / 32)
+ *    rows beyond 4 output blocks).
+ * A launch over a stripe with few tiles then runs one wave per (tile, part)
+ * instead of one per tile, which gives short stripes more waves and each
+ * wave a shorter chain of records and a deeper load ring, at the cost of
+ * reading each input once per part that needs it (mostly from the caches).
+ * Batches (ec_batch_*) use block parts only. */
 enum {
-  EC_SPLIT_AUTO = 0,   /* split when one wave per (tile, part) fits in the waves the chip
-                          keeps resident for the program's slot budget (default) */
-  EC_SPLIT_NEVER = 1,  /* one wave per tile */
-  EC_SPLIT_ALWAYS = 2  /* one wave per (tile, part) whenever the program has parts */
+  EC_SPLIT_AUTO = 0,   /* row parts when one wave per (tile, row part) fits in the waves the
+                          chip keeps resident for the program's slot budget, else block
+                          parts when one wave per (tile, block part) does (default) */
+  EC_SPLIT_NEVER = 1,  /* one wave per tile; no parts are built */
+  EC_SPLIT_ALWAYS = 2, /* block parts on every launch when the program has them */
+  EC_SPLIT_ROWS = 3    /* row parts on every single-stripe launch when the program has them
+                          (batches: as EC_SPLIT_ALWAYS) */
 };
 
 typedef struct {
@@ -119,7 +128,8 @@ typedef struct {
   uint32_t n_records;   /* executor records per tile */
   uint32_t n_ops;       /* slot XORs per tile (the executor's unit of work) */
   uint32_t n_words;     /* bytecode words */
-  uint32_t n_parts;     /* parts for the row split (0: none, e.g. one output block) */
+  uint32_t n_parts;     /* block parts for the row split (0: none, e.g. one output block) */
+  uint32_t n_row_parts; /* row parts for the row split (0: none) */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
 } ec_program_info;
@@ -216,9 +226,11 @@ ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream str
 /* The device bytecode the executor runs per tile (host copy). */
 ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, size_t *n_words);
 
-/* The bytecode of part `part` (0 <= part < info.n_parts) of a program
- * (host copy; same record format as ec_program_bytecode, storing only the
- * part's output blocks).  EC_ERR_ARG for a part that does not exist. */
+/* The bytecode of part `part` of a program: block part `part` for
+ * 0 <= part < info.n_parts, then row part `part - n_parts` for
+ * part < n_parts + n_row_parts (host copy; same record format as
+ * ec_program_bytecode, storing only the part's output rows).  EC_ERR_ARG for
+ * a part that does not exist. */
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words);
 
 /* ---- batched execution: many stripes, one persistent launch */

@@ -20,11 +20,12 @@ __all__ = [
     "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_device_copy", "lib",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
+    "SPLIT_ROWS",
 ]
 
 LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
 COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
-SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS = 0, 1, 2
+SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS, SPLIT_ROWS = 0, 1, 2, 3
 STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
 
 STATUS = {
@@ -54,7 +55,8 @@ class CompileOpts(ctypes.Structure):
 class ProgramInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
-        "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts")] + [
+        "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts",
+        "n_row_parts")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
 
 
@@ -240,7 +242,9 @@ class Program:
         return [w[i] for i in range(n.value)]
 
     def part_bytecode(self, part: int):
-        """Words of row-split part ``part`` (0 <= part < info["n_parts"])."""
+        """Words of row-split part ``part``: block parts first
+        (``part < info["n_parts"]``), then row parts (up to
+        ``n_parts + n_row_parts``)."""
         w = ctypes.POINTER(ctypes.c_uint32)()
         n = ctypes.c_size_t()
         _check(lib().ec_program_part_bytecode(self._h, part, ctypes.byref(w), ctypes.byref(n)),

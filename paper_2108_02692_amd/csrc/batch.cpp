@@ -178,15 +178,17 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     in_bytes += (size_t)n_in * st.block_bytes;
     out_bytes += (size_t)n_out * st.block_bytes;
   }
-  // Row split (the programs' parts) when one wave per (tile, part) of the
-  // whole batch fits in one round of resident waves, as for one stripe.
+  // Row split (the programs' parts of whole output blocks; batches do not
+  // use the single-row parts) when one wave per (tile, part) of the whole
+  // batch fits in one round of resident waves, as for one stripe.
   const uint64_t resident_waves = 4ull * (uint64_t)b->n_cus * waves_per_simd(slots);
   const bool fits = tiles_split <= resident_waves;
   for (int s = 0; s < n_stripes; ++s) {
     const ec_program *prog = stripes[s].prog;
     StripeDesc &d = desc[s];
     const bool split = !prog->parts.empty() &&
-                       (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && fits));
+                       (prog->split == EC_SPLIT_ALWAYS || prog->split == EC_SPLIT_ROWS ||
+                        (prog->split == EC_SPLIT_AUTO && fits));
     const uint32_t n_parts = split ? (uint32_t)prog->parts.size() : 1u;
     for (uint32_t q = 0; q < (uint32_t)kMaxParts; ++q)
       d.part_off[q] = split && q < n_parts ? prog->part_off[q] : 0u;

@@ -106,19 +106,31 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   const int n_cus = device_cus();
   if (n_cus <= 0) return EC_ERR_DEVICE;
   const uint64_t resident = (uint64_t)n_cus * waves_per_simd(prog->slots);  // workgroups of 4 waves
-  // Row split for short stripes: when one wave per (tile, part) still fits
-  // in one round of resident waves.  Measured on RS(10,4) encodes, 4 parts:
-  // 30-31 us -> 23 us per launch for blocks up to 2 MiB (256 tiles),
-  // 31.0 -> 28.4 us at 4 MiB, but 32 -> 47 us at 8 MiB: every part reads
-  // every input, so once the waves are busy anyway the split only adds work.
+  // Row split for short stripes, when one wave per (tile, part) still fits
+  // in one round of resident waves: single-row parts first, else parts of
+  // whole output blocks.  Measured on RS(10,4) encodes (32 row parts or 4
+  // block parts against one wave per tile): 8 KiB - 256 KiB blocks 12.0 -
+  // 12.3 us with row parts, 22.5 - 23.0 us with block parts, 28.5 - 30.5 us
+  // unsplit; 1 MiB 25.7 us with row parts forced, 23.3 us with block parts;
+  // 8 MiB 47 us with block parts forced against 32 us unsplit: every part
+  // reads its inputs, so once the waves are busy anyway a split only adds
+  // work.
   a.n_parts = 1;
   a.part_off[0] = 0;
-  const uint64_t parts = prog->parts.size();
-  const bool split = parts > 0 && (prog->split == EC_SPLIT_ALWAYS ||
-                                   (prog->split == EC_SPLIT_AUTO && (uint64_t)a.n_tiles * parts <= 4 * resident));
-  if (split) {
-    a.n_parts = (uint32_t)prog->parts.size();
-    for (uint32_t q = 0; q < a.n_parts; ++q) a.part_off[q] = prog->part_off[q];
+  const uint64_t waves = 4 * resident;
+  const std::vector<uint32_t> *off = nullptr;
+  const uint64_t nb = prog->parts.size(), nr = prog->row_parts.size();
+  if (prog->split == EC_SPLIT_ROWS) {
+    if (nr) off = &prog->row_part_off;
+  } else if (prog->split == EC_SPLIT_ALWAYS) {
+    if (nb) off = &prog->part_off;
+  } else if (prog->split == EC_SPLIT_AUTO) {
+    if (nr && a.n_tiles * nr <= waves) off = &prog->row_part_off;
+    else if (nb && a.n_tiles * nb <= waves) off = &prog->part_off;
+  }
+  if (off) {
+    a.n_parts = (uint32_t)off->size();
+    for (uint32_t q = 0; q < a.n_parts; ++q) a.part_off[q] = (*off)[q];
   }
   // As many workgroups as stay resident (4 waves each, one per SIMD, times
   // the waves per SIMD the slot budget allows), each looping over its work
@@ -169,7 +181,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
-  if (o.split > EC_SPLIT_ALWAYS) return EC_ERR_UNSUPPORTED;
+  if (o.split > EC_SPLIT_ROWS) return EC_ERR_UNSUPPORTED;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -266,32 +278,49 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   prog->slots = po.slots;
   if (!simulate_code(prog->code.words, prog->slots, n_in, n_out, brows)) return EC_ERR_UNSUPPORTED;
 
-  // Row-split parts: groups of whole output blocks, each scheduled alone on
-  // the same slot budget (so with a deeper load ring); checked like the
-  // whole program, and dropped if any group does not fit in one pass.
+  // Row-split parts at two granularities, each part scheduled alone on the
+  // same slot budget (so with a deeper load ring) and checked like the whole
+  // program; a set is dropped if any of its parts does not fit in one pass:
+  //  * groups of whole output blocks (at most kMaxParts): mid-size stripes
+  //    and batches;
+  //  * groups of ceil(rows / kMaxRowParts) bit rows (one row each for up to
+  //    4 output blocks): the shortest stripes, where a wave's time is its
+  //    chain of records and a single row needs only about half the inputs.
   prog->split = (int)o.split;
   prog->image = prog->code.words;
   prog->part_off.clear();
-  if (n_out > 1 && o.split != EC_SPLIT_NEVER) {
-    const int groups = std::min(n_out, kMaxParts);
+  prog->row_part_off.clear();
+  const int n_rows = 8 * n_out;
+  auto build_parts = [&](int unit, int max_groups, std::vector<PushCode> &set) -> bool {
+    const int units = n_rows / unit;
+    const int groups = std::min(units, max_groups);
     for (int g = 0; g < groups; ++g) {
       PushOpts pp = po;
-      pp.row_lo = 8 * (g * n_out / groups);
-      pp.row_hi = 8 * ((g + 1) * n_out / groups);
+      pp.row_lo = unit * (g * units / groups);
+      pp.row_hi = unit * ((g + 1) * units / groups);
       pp.max_ring = 24;
       PushCode part;
       if (push_schedule(dag, n_in, pp, part) != 0 || part.passes != 1) {
-        prog->parts.clear();
-        break;
+        set.clear();
+        return true;
       }
-      if (!simulate_code(part.words, prog->slots, n_in, n_out, brows, pp.row_lo, pp.row_hi))
-        return EC_ERR_UNSUPPORTED;
-      prog->parts.push_back(std::move(part));
+      if (!simulate_code(part.words, prog->slots, n_in, n_out, brows, pp.row_lo, pp.row_hi)) return false;
+      set.push_back(std::move(part));
     }
-    for (const PushCode &part : prog->parts) {
-      prog->part_off.push_back((uint32_t)prog->image.size());
-      prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
-    }
+    return true;
+  };
+  if (o.split != EC_SPLIT_NEVER) {
+    if (n_out > 1 && !build_parts(8, kMaxParts, prog->parts)) return EC_ERR_UNSUPPORTED;
+    const int unit = (n_rows + kMaxRowParts - 1) / kMaxRowParts;
+    if (n_rows > 1 && !build_parts(unit, kMaxRowParts, prog->row_parts)) return EC_ERR_UNSUPPORTED;
+  }
+  for (const PushCode &part : prog->parts) {
+    prog->part_off.push_back((uint32_t)prog->image.size());
+    prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
+  }
+  for (const PushCode &part : prog->row_parts) {
+    prog->row_part_off.push_back((uint32_t)prog->image.size());
+    prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
   ec_program_info &info = prog->info;
@@ -315,6 +344,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_ops = (uint32_t)prog->code.n_ops;
   info.n_words = (uint32_t)prog->code.words.size();
   info.n_parts = (uint32_t)prog->parts.size();
+  info.n_row_parts = (uint32_t)prog->row_parts.size();
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -405,9 +435,12 @@ ec_status ec_program_upload(ec_program *prog) {
 }
 
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words) {
-  if (!prog || !words || !n_words || part < 0 || part >= (int)prog->parts.size()) return EC_ERR_ARG;
-  *words = prog->parts[part].words.data();
-  *n_words = prog->parts[part].words.size();
+  if (!prog || !words || !n_words || part < 0) return EC_ERR_ARG;
+  const int nb = (int)prog->parts.size();
+  if (part >= nb + (int)prog->row_parts.size()) return EC_ERR_ARG;
+  const PushCode &c = part < nb ? prog->parts[part] : prog->row_parts[part - nb];
+  *words = c.words.data();
+  *n_words = c.words.size();
   return EC_OK;
 }
 

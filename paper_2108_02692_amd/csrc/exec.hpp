@@ -8,7 +8,8 @@ namespace ec {
 
 constexpr int kMaxBlocks = 32;  // input + output blocks of one stripe
 constexpr int kTileBytes = 1024;  // bytes of each strip per wave (64 lanes x 16 B)
-constexpr int kMaxParts = 8;      // row-split parts of one program
+constexpr int kMaxParts = 8;      // row-split parts of whole output blocks
+constexpr int kMaxRowParts = 32;  // row-split parts of single bit rows (or small groups)
 
 // Kernel arguments of a single-stripe launch (passed by value).
 struct ExecArgs {
@@ -25,7 +26,7 @@ struct ExecArgs {
   // part_off[k % n_parts] of prog) on tile k / n_parts; n_parts = 1 and
   // part_off[0] = 0 run the whole program on every tile.
   uint32_t n_parts;
-  uint32_t part_off[kMaxParts];
+  uint32_t part_off[kMaxRowParts];
 };
 
 // One stripe of a batched launch (device memory, read-only during a launch).

@@ -505,9 +505,10 @@ int peak_open_temps(const PushDag &d) {
 int push_schedule(const PushDag &d, int n_in_blocks, const PushOpts &opts, PushCode &out) {
   const int K = opts.slots;
   const int R = opts.row_hi < 0 ? d.n_rows : std::min(opts.row_hi, d.n_rows);
-  if (opts.row_lo < 0 || opts.row_lo % 8 || (opts.row_lo >= R && R > 0)) return -1;
-  // Passes: as many whole output blocks per pass as fit beside the pass's
-  // open temporaries and a ring of at least two strips.
+  if (opts.row_lo < 0 || (opts.row_lo >= R && R > 0)) return -1;
+  // Passes: as many rows per pass, in steps of 8 from row_lo (whole output
+  // blocks when row_lo is a block boundary), as fit beside the pass's open
+  // temporaries and a ring of at least two strips.
   std::vector<Pass> passes;
   for (int r0 = opts.row_lo; r0 < R;) {
     int take = 0;

@@ -62,8 +62,8 @@ struct PushOpts {
   int slots = 40;     // register slots (16 B per lane each)
   int max_ring = 12;  // most input strips loaded ahead of their use
   int prefetch = 0;   // strips touched this far ahead of their register load (0 = none)
-  int row_lo = 0;     // rows scheduled: [row_lo, row_hi), whole output blocks
-  int row_hi = -1;    // (-1: every row)
+  int row_lo = 0;     // rows scheduled: [row_lo, row_hi) (whole output blocks
+  int row_hi = -1;    // or any run of rows; -1: every row)
 };
 
 struct PushCode {

@@ -258,6 +258,9 @@ def test_compile_errors():
         E.ec_compile_slp(10, 4, gen, block_strips=81)
     assert e.value.name == "EC_ERR_ARG"
     with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_ROWS + 1)
+    assert e.value.name == "EC_ERR_UNSUPPORTED"
+    with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
     assert e.value.name == "EC_ERR_ARG"
 
@@ -267,23 +270,32 @@ def test_compile_errors():
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
 def test_row_split_parts_cover_the_rows(n, p, er, level):
     """Every row-split part, run by the independent simulator, stores only its
-    own output blocks; together they store every output strip with the
-    bitmatrix row's value, exactly once."""
+    own output rows; the block parts together, and the row parts together,
+    store every output strip with the bitmatrix row's value, exactly once."""
     gen = E.ec_matrix_cauchy(n, p)
     rows = oracle_rows(gen, n, p, er)
     prog = E.ec_compile_slp(n, p, gen, er, level=level)
     n_out = len(prog.out_blocks)
-    n_parts = prog.info["n_parts"]
+    n_parts, n_row_parts = prog.info["n_parts"], prog.info["n_row_parts"]
     assert n_parts == (min(n_out, 8) if n_out > 1 else 0) or n_parts == 0
-    got = {}
-    for q in range(n_parts):
-        part = simulate(prog.part_bytecode(q), prog.info["slots"], len(prog.in_blocks), n_out)
-        assert part and not set(part) & set(got)
-        # a part holds whole output blocks
-        assert all(8 * (o // 8) + j in part for o in part for j in range(8))
-        got.update(part)
-    if n_parts:
-        assert [got[o] for o in range(len(rows))] == rows
-    assert E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_NEVER).info["n_parts"] == 0
+    assert n_row_parts == min(8 * n_out, 32) or n_row_parts == 0
+    unit = -(-8 * n_out // 32)  # rows per row part
+    for lo, hi, whole_blocks in ((0, n_parts, True), (n_parts, n_parts + n_row_parts, False)):
+        got = {}
+        for q in range(lo, hi):
+            part = simulate(prog.part_bytecode(q), prog.info["slots"], len(prog.in_blocks), n_out)
+            assert part and not set(part) & set(got)
+            if whole_blocks:
+                assert all(8 * (o // 8) + j in part for o in part for j in range(8))
+            else:  # a run of whole units of rows, after the previous part's
+                assert sorted(part) == list(range(len(got), len(got) + len(part)))
+                assert len(part) % unit == 0
+            got.update(part)
+        if hi > lo:
+            assert [got[o] for o in range(len(rows))] == rows
+    info = E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_NEVER).info
+    assert info["n_parts"] == 0 and info["n_row_parts"] == 0
     with pytest.raises(E.EcError):
-        prog.part_bytecode(n_parts)
+        prog.part_bytecode(n_parts + n_row_parts)
+    with pytest.raises(E.EcError):
+        prog.part_bytecode(-1)

@@ -328,18 +328,19 @@ def test_launch_argument_errors():
     assert e.value.name == "EC_ERR_ARG"
 
 
-@pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, ()), (14, 4, (0, 13))])
+@pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, ()), (14, 4, (0, 13)), (2, 1, ()),
+                                    (4, 12, ())])
 def test_row_split_matches_oracle(n, p, er):
-    """Short stripes run one wave per (tile, part): the split forced on, off
-    and left to the library, on ragged and small block sizes, equal the
-    oracle."""
+    """Short stripes run one wave per (tile, part): row parts and block parts
+    forced, the split off and left to the library, on ragged and small block
+    sizes, equal the oracle."""
     gen = E.ec_matrix_cauchy(n, p)
     G = np.array(gen, dtype=np.uint8)
     for S in (4096 + 128, 1 << 20, 3 * (1 << 20) + 384):
         data = W.host_blocks(n, S, seed=S % 1000 + n)
         blocks = data + oracle.encode(G, n, p, data)
         want = [blocks[e] for e in er] if er else blocks[n:]
-        for split in (E.SPLIT_ALWAYS, E.SPLIT_NEVER, E.SPLIT_AUTO):
+        for split in (E.SPLIT_ROWS, E.SPLIT_ALWAYS, E.SPLIT_NEVER, E.SPLIT_AUTO):
             prog = E.ec_compile_slp(n, p, gen, list(er), split=split)
             got = run_decode(prog, blocks, S) if er else run_encode(prog, data, S)
             assert_blocks_equal(got, want, "RS(%d,%d) %s S=%d split %d" % (n, p, er, S, split))
@@ -352,7 +353,7 @@ def test_random_cases_match_oracle():
     rng = random.Random(2024)
     budgets = (0, 24, 32, 36, 38, 40, 44, 48)
     levels = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED)
-    splits = (E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS)
+    splits = (E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS, E.SPLIT_ROWS)
     done = 0
     while done < 40:
         n = rng.randint(1, 20)
