@@ -82,13 +82,27 @@ def time_launches(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps
 
 
-def code_sha(path):
-    """sha256 of a C++/HIP source with comments and blank lines removed, so
+def code_sha(*paths):
+    """sha256 of C++/HIP sources with comments and blank lines removed, so
     that an edit of comments alone keeps a measurement valid."""
-    text = open(path).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines()]
-    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()
+    out = []
+    for path in paths:
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines()]
+        out.append("\n".join(ln for ln in lines if ln.strip()))
+    return hashlib.sha256("\n".join(out).encode()).hexdigest()
+
+
+# The executor's kernels and everything their code depends on (the kernel
+# arguments' layout, the record format).
+EXECUTOR_SOURCES = ("exec.hip", "exec.hpp", "bytecode.hpp")
+
+
+def executor_sha():
+    import paper_2108_02692_amd
+    csrc = os.path.join(os.path.dirname(paper_2108_02692_amd.__file__), "csrc")
+    return code_sha(*[os.path.join(csrc, f) for f in EXECUTOR_SOURCES])
 
 
 def program_sha(prog):
@@ -100,8 +114,7 @@ def program_sha(prog):
 def measured_traffic(prog):
     """HBM bytes per launch from the committed byte-counter profile of this
     workload, if it was taken on this executor and this program (else None)."""
-    import paper_2108_02692_amd
-    exec_sha = code_sha(os.path.join(os.path.dirname(paper_2108_02692_amd.__file__), "csrc", "exec.hip"))
+    exec_sha = executor_sha()
     psha = program_sha(prog)
     if not os.path.isdir(PROFILES):
         return None
@@ -111,7 +124,7 @@ def measured_traffic(prog):
         with open(os.path.join(PROFILES, name)) as f:
             for m in re.finditer(r"<!-- traffic (\{.*?\}) -->", f.read()):
                 rec = json.loads(m.group(1))
-                if rec.get("exec_hip_code_sha256") == exec_sha and rec.get("program_sha256") == psha:
+                if rec.get("executor_code_sha256") == exec_sha and rec.get("program_sha256") == psha:
                     return rec["fetch_bytes"] + rec["write_bytes"]
     return None
 
