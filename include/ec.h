@@ -176,7 +176,9 @@ ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uin
 
 /* Copy the program's records to the current device now (synchronously, one
  * small allocation per device and program).  Otherwise the first launch on
- * a device does it, which a latency-sensitive caller may not want.
+ * a device does it, which a latency-sensitive caller may not want.  Once a
+ * program is on the device, ec_encode / ec_decode with it only enqueue one
+ * kernel and may be captured into a HIP graph.
  * Errors: EC_ERR_ARG, EC_ERR_NOMEM, EC_ERR_DEVICE. */
 ec_status ec_program_upload(ec_program *prog);
 

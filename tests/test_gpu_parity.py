@@ -303,6 +303,46 @@ def test_two_streams_concurrently():
     assert_blocks_equal([x.cpu().numpy() for x in pb], oracle.encode(G, n, p, db), "stream b")
 
 
+@pytest.mark.parametrize("S", [256 << 10, 4 << 20])
+def test_graph_captured_launches_replay(S):
+    """ec_encode and ec_decode captured in a HIP graph (after uploading the
+    programs) and replayed three times, with new input bytes and poisoned
+    outputs written eagerly between the replays: every replay equals the
+    oracle on that replay's inputs (256 KiB blocks take row parts, 4 MiB
+    block parts)."""
+    n, p, er = 10, 4, [2, 4, 5, 11]
+    gen = E.ec_matrix_cauchy(n, p)
+    G = np.array(gen, dtype=np.uint8)
+    enc = E.ec_compile_slp(n, p, gen)
+    dec = E.ec_compile_slp(n, p, gen, er)
+    enc.upload()
+    dec.upload()
+    d, par = W.empty_blocks(n, S), W.empty_blocks(p, S)
+    surv, rec = W.empty_blocks(len(dec.in_blocks), S), W.empty_blocks(len(dec.out_blocks), S)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        E.ec_encode(enc, d, par, S, s)
+        E.ec_decode(dec, surv, rec, S, s)
+    for rep in range(3):
+        data = W.host_blocks(n, S, seed=100 + rep)
+        blocks = data + oracle.encode(G, n, p, data)
+        for t, x in zip(d, data):
+            t.copy_(torch.from_numpy(x))
+        for t, b in zip(surv, dec.in_blocks):
+            t.copy_(torch.from_numpy(blocks[b]))
+        for t in par + rec:
+            t.fill_(0x3C + rep)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        assert_blocks_equal([x.cpu().numpy() for x in par], blocks[n:], "graph encode replay %d" % rep)
+        assert_blocks_equal([x.cpu().numpy() for x in rec], [blocks[e] for e in dec.out_blocks],
+                            "graph decode replay %d" % rep)
+
+
 def test_launch_argument_errors():
     n, p, S = 10, 4, 4096
     gen = E.ec_matrix_cauchy(n, p)
