@@ -90,7 +90,8 @@ typedef struct {
 
 /* Row split.  Unless compiled with EC_SPLIT_NEVER, a program also carries
  * "parts": independent programs that each compute some of the output rows
- * from the inputs they need, in two sets:
+ * from the inputs they need (scheduled from the plain bitmatrix rows, which
+ * make the shortest chains of records, whatever the level), in two sets:
  *  - block parts: up to 8, each a group of whole output blocks (only when
  *    there is more than one output block);
  *  - row parts: up to 32, each one bit row (groups of ceil(8 n_out / 32)

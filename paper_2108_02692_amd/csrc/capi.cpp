@@ -286,6 +286,12 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   //  * groups of ceil(rows / kMaxRowParts) bit rows (one row each for up to
   //    4 output blocks): the shortest stripes, where a wave's time is its
   //    chain of records and a single row needs only about half the inputs.
+  // Parts run where a lone wave's chain of records is the time, and there
+  // the plain rows win whatever the level: one record per input strip and
+  // no records for temporaries (measured on RS(10,4) encodes, 8 KiB - 1 MiB
+  // blocks: row parts 10.5-10.8 us plain against 11.8-12.1 us compressed,
+  // block parts 20.2-20.7 against 22.3-22.9 us; 2-20% on every codec tried).
+  const PushDag pdag = o.level == EC_LEVEL_PLAIN ? dag : push_plain(brows, n_const);
   prog->split = (int)o.split;
   prog->image = prog->code.words;
   prog->part_off.clear();
@@ -300,7 +306,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
       pp.row_hi = unit * ((g + 1) * units / groups);
       pp.max_ring = 24;
       PushCode part;
-      if (push_schedule(dag, n_in, pp, part) != 0 || part.passes != 1) {
+      if (push_schedule(pdag, n_in, pp, part) != 0 || part.passes != 1) {
         set.clear();
         return true;
       }
