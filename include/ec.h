@@ -94,8 +94,8 @@ typedef struct {
  * make the shortest chains of records, whatever the level), in two sets:
  *  - block parts: up to 8, each a group of whole output blocks (only when
  *    there is more than one output block);
- *  - row parts: up to 32, each one bit row (groups of ceil(8 n_out / 32)
- *    rows beyond 4 output blocks).
+ *  - row parts: up to 32, each one bit row (beyond 4 output blocks, runs
+ *    of floor or ceil(8 n_out / 32) consecutive rows).
  * A launch over a stripe with few tiles then runs one wave per (tile, part)
  * instead of one per tile, which gives short stripes more waves and each
  * wave a shorter chain of records and a deeper load ring, at the cost of

@@ -283,9 +283,10 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   // program; a set is dropped if any of its parts does not fit in one pass:
   //  * groups of whole output blocks (at most kMaxParts): mid-size stripes
   //    and batches;
-  //  * groups of ceil(rows / kMaxRowParts) bit rows (one row each for up to
-  //    4 output blocks): the shortest stripes, where a wave's time is its
-  //    chain of records and a single row needs only about half the inputs.
+  //  * single bit rows, or runs of floor or ceil(rows / kMaxRowParts) rows
+  //    beyond 4 output blocks (at most kMaxRowParts): the shortest stripes,
+  //    where a wave's time is its chain of records and a single row needs
+  //    only about half the inputs.
   // Parts run where a lone wave's chain of records is the time, and there
   // the plain rows win whatever the level: one record per input strip and
   // no records for temporaries (measured on RS(10,4) encodes, 8 KiB - 1 MiB
@@ -297,8 +298,11 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   prog->part_off.clear();
   prog->row_part_off.clear();
   const int n_rows = 8 * n_out;
+  // Groups of whole units of `unit` rows; consecutive groups differ by at
+  // most one unit and together cover every row.
   auto build_parts = [&](int unit, int max_groups, std::vector<PushCode> &set) -> bool {
     const int units = n_rows / unit;
+    if (units * unit != n_rows) return false;
     const int groups = std::min(units, max_groups);
     for (int g = 0; g < groups; ++g) {
       PushOpts pp = po;
@@ -317,8 +321,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   };
   if (o.split != EC_SPLIT_NEVER) {
     if (n_out > 1 && !build_parts(8, kMaxParts, prog->parts)) return EC_ERR_UNSUPPORTED;
-    const int unit = (n_rows + kMaxRowParts - 1) / kMaxRowParts;
-    if (n_rows > 1 && !build_parts(unit, kMaxRowParts, prog->row_parts)) return EC_ERR_UNSUPPORTED;
+    if (n_rows > 1 && !build_parts(1, kMaxRowParts, prog->row_parts)) return EC_ERR_UNSUPPORTED;
   }
   for (const PushCode &part : prog->parts) {
     prog->part_off.push_back((uint32_t)prog->image.size());

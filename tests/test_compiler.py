@@ -266,7 +266,8 @@ def test_compile_errors():
 
 
 @pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, (1, 7)), (14, 4, (0, 13)),
-                                    (28, 4, ()), (4, 12, ()), (10, 2, (8, 9))])
+                                    (28, 4, ()), (4, 12, ()), (10, 2, (8, 9)), (2, 10, ()), (3, 13, ()),
+                                    (4, 12, tuple(range(1, 12))), (20, 9, ())])
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
 def test_row_split_parts_cover_the_rows(n, p, er, level):
     """Every row-split part, run by the independent simulator, stores only its
@@ -279,7 +280,7 @@ def test_row_split_parts_cover_the_rows(n, p, er, level):
     n_parts, n_row_parts = prog.info["n_parts"], prog.info["n_row_parts"]
     assert n_parts == (min(n_out, 8) if n_out > 1 else 0) or n_parts == 0
     assert n_row_parts == min(8 * n_out, 32) or n_row_parts == 0
-    unit = -(-8 * n_out // 32)  # rows per row part
+    lo_rows, hi_rows = 8 * n_out // 32, -(-8 * n_out // 32)  # rows per row part
     for lo, hi, whole_blocks in ((0, n_parts, True), (n_parts, n_parts + n_row_parts, False)):
         got = {}
         for q in range(lo, hi):
@@ -287,9 +288,9 @@ def test_row_split_parts_cover_the_rows(n, p, er, level):
             assert part and not set(part) & set(got)
             if whole_blocks:
                 assert all(8 * (o // 8) + j in part for o in part for j in range(8))
-            else:  # a run of whole units of rows, after the previous part's
+            else:  # a run of rows right after the previous part's, of even size
                 assert sorted(part) == list(range(len(got), len(got) + len(part)))
-                assert len(part) % unit == 0
+                assert len(part) in (max(1, lo_rows), hi_rows)
             got.update(part)
         if hi > lo:
             assert [got[o] for o in range(len(rows))] == rows

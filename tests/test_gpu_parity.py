@@ -369,7 +369,7 @@ def test_launch_argument_errors():
 
 
 @pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, ()), (14, 4, (0, 13)), (2, 1, ()),
-                                    (4, 12, ())])
+                                    (4, 12, ()), (2, 10, ()), (4, 12, tuple(range(1, 12)))])
 def test_row_split_matches_oracle(n, p, er):
     """Short stripes run one wave per (tile, part): row parts and block parts
     forced, the split off and left to the library, on ragged and small block
