@@ -100,15 +100,15 @@ typedef struct {
  * instead of one per tile, which gives short stripes more waves and each
  * wave a shorter chain of records and a deeper load ring, at the cost of
  * reading each input once per part that needs it (mostly from the caches).
- * Batches (ec_batch_*) use block parts only. */
+ * A batch (ec_batch_*) decides for all its EC_SPLIT_AUTO stripes at once,
+ * by the same rule over the work items of the whole batch. */
 enum {
   EC_SPLIT_AUTO = 0,   /* row parts when one wave per (tile, row part) fits in the waves the
                           chip keeps resident for the program's slot budget, else block
                           parts when one wave per (tile, block part) does (default) */
   EC_SPLIT_NEVER = 1,  /* one wave per tile; no parts are built */
   EC_SPLIT_ALWAYS = 2, /* block parts on every launch when the program has them */
-  EC_SPLIT_ROWS = 3    /* row parts on every single-stripe launch when the program has them
-                          (batches: as EC_SPLIT_ALWAYS) */
+  EC_SPLIT_ROWS = 3    /* row parts on every launch when the program has them */
 };
 
 typedef struct {

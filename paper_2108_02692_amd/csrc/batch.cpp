@@ -145,7 +145,7 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   std::vector<std::pair<uintptr_t, uintptr_t>> reads, writes;
   int slots = 0;
   size_t in_bytes = 0, out_bytes = 0;
-  uint64_t tiles_split = 0;  // work items of the batch with the row split
+  uint64_t items_rows = 0, items_blocks = 0;  // work items with row parts, with block parts
   for (int s = 0; s < n_stripes; ++s) {
     const ec_stripe &st = stripes[s];
     const ec_program *prog = st.prog;
@@ -174,24 +174,29 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     d.n_blocks = (uint32_t)(n_in + n_out);
     d.strip_len = (uint32_t)(st.block_bytes / 8);
     const uint64_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
-    tiles_split += n_tiles * std::max<size_t>(1, prog->parts.size());
+    items_rows += n_tiles * std::max<size_t>(1, prog->row_parts.size());
+    items_blocks += n_tiles * std::max<size_t>(1, prog->parts.size());
     in_bytes += (size_t)n_in * st.block_bytes;
     out_bytes += (size_t)n_out * st.block_bytes;
   }
-  // Row split (the programs' parts of whole output blocks; batches do not
-  // use the single-row parts) when one wave per (tile, part) of the whole
-  // batch fits in one round of resident waves, as for one stripe.
+  // Row split as for one stripe, decided for the whole batch: row parts
+  // when one wave per (tile, row part) of every stripe fits in one round of
+  // resident waves, else block parts when one wave per (tile, block part)
+  // does, else none (stripes compiled with EC_SPLIT_ROWS / ALWAYS / NEVER
+  // take their own choice).
   const uint64_t resident_waves = 4ull * (uint64_t)b->n_cus * waves_per_simd(slots);
-  const bool fits = tiles_split <= resident_waves;
+  const bool rows_fit = items_rows <= resident_waves;
+  const bool blocks_fit = !rows_fit && items_blocks <= resident_waves;
   for (int s = 0; s < n_stripes; ++s) {
     const ec_program *prog = stripes[s].prog;
     StripeDesc &d = desc[s];
-    const bool split = !prog->parts.empty() &&
-                       (prog->split == EC_SPLIT_ALWAYS || prog->split == EC_SPLIT_ROWS ||
-                        (prog->split == EC_SPLIT_AUTO && fits));
-    const uint32_t n_parts = split ? (uint32_t)prog->parts.size() : 1u;
-    for (uint32_t q = 0; q < (uint32_t)kMaxParts; ++q)
-      d.part_off[q] = split && q < n_parts ? prog->part_off[q] : 0u;
+    const std::vector<uint32_t> *off = nullptr;
+    if (prog->split == EC_SPLIT_ROWS || (prog->split == EC_SPLIT_AUTO && rows_fit))
+      off = prog->row_parts.empty() ? nullptr : &prog->row_part_off;
+    else if (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && blocks_fit))
+      off = prog->parts.empty() ? nullptr : &prog->part_off;
+    const uint32_t n_parts = off ? (uint32_t)off->size() : 1u;
+    for (uint32_t q = 0; q < (uint32_t)kMaxRowParts; ++q) d.part_off[q] = off && q < n_parts ? (*off)[q] : 0u;
     const uint32_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
     const uint32_t n_its = (n_tiles + tiles_per_item - 1) / tiles_per_item;
     // Strips a multiple of 4 MiB apart: consecutive items from 8 distant

@@ -35,8 +35,8 @@ struct StripeDesc {
   const uint32_t *prog;          // the stripe's device image
   uint32_t n_blocks;             // input + output blocks
   uint32_t strip_len;            // bytes per strip
-  uint32_t part_off[kMaxParts];  // word offset in prog of each part a work item may name
-};                               // (part 0 at offset 0: the whole program, when not split)
+  uint32_t part_off[kMaxRowParts];  // word offset in prog of each part a work item may name
+};                                  // (part 0 at offset 0: the whole program, when not split)
 
 // Second word of a work item: first tile in the low bits, part above.
 constexpr uint32_t kItemPartShift = 24;
