@@ -45,6 +45,7 @@ extern "C" {
 
 typedef struct ec_program ec_program; /* compiled program: host IR + device bytecode */
 typedef struct ec_batch ec_batch;     /* prepared multi-stripe launch */
+typedef struct ec_server ec_server;   /* serving loop: streams, events and reusable batches */
 typedef struct ihipStream_t *ec_stream; /* a hipStream_t */
 
 typedef enum {
@@ -56,7 +57,8 @@ typedef enum {
   EC_ERR_NOMEM = 5,             /* host or device allocation failed */
   EC_ERR_DEVICE = 6,            /* HIP runtime error (no device, launch failure) */
   EC_ERR_UNSUPPORTED = 7,       /* option or size outside what the executor supports */
-  EC_ERR_CAPACITY = 8           /* program does not fit the register slot budget */
+  EC_ERR_CAPACITY = 8           /* program does not fit the register slot budget; or a
+                                   request does not fit a server's budget or arena */
 } ec_status;
 
 /* Optimisation level of a compiled program (the stages of Sec. 7.5). */
@@ -289,6 +291,70 @@ ec_status ec_batch_reserve(ec_batch *batch, int n_stripes, size_t n_items);
 ec_status ec_batch_query(const ec_batch *batch, size_t *n_items, size_t *in_bytes, size_t *out_bytes);
 
 void ec_batch_free(ec_batch *batch);
+
+/* ---- serving: a request loop with continuous batching
+ *
+ * Not part of the paper's method (which codes one stripe at a time): the
+ * loop that serves a stream of independent encode and decode requests with
+ * the programs above.  ec_server_run admits arrived requests, in arrival
+ * order, while their input + output bytes fit budget_bytes (counting every
+ * request in flight) and their outputs fit a first-fit arena in the
+ * caller's device buffer; packs the admitted requests (up to max_batch, of
+ * one slot budget) into one launch on a free slot's stream, a plain
+ * ec_encode / ec_decode launch for one request and a reusable ec_batch for
+ * more; and keeps admitting while earlier launches run, so requests
+ * admitted meanwhile overlap with them on the device.  Completion is found
+ * by polling each busy slot's event, on the caller's thread, without
+ * sleeping (the loop holds one host core while it runs). */
+
+typedef struct {
+  double arrival_s;          /* arrival, seconds after the run starts; nondecreasing over a run */
+  const ec_program *prog;    /* encode or decode program */
+  const uint8_t *const *in;  /* prog's n_in device input pointers (info.in_blocks order); they
+                                must not overlap any output placed in the arena */
+  size_t block_bytes;        /* multiple of 128 */
+} ec_request;
+
+typedef struct {
+  size_t budget_bytes; /* admission limit on the input + output bytes of requests in flight */
+  int n_slots;         /* launches in flight, one stream each: 1..16 */
+  int max_batch;       /* requests per launch: >= 1 */
+} ec_serve_opts;
+
+/* Called on the loop's thread when a launch has completed, before its
+ * requests' output space is reused: the requests' indices in the run's
+ * array and the byte offsets of their outputs in the arena (output j of a
+ * request with block_bytes b at offset + j * b). */
+typedef void (*ec_serve_done_fn)(void *user, const int *ids, int n_ids, const size_t *out_off);
+
+/* A server over the caller's device arena (16-byte aligned, at least 4 KiB;
+ * it must outlive the server) on the current device: creates n_slots
+ * streams (default priority, non-blocking), their events and batches.
+ * Errors: EC_ERR_ARG, EC_ERR_ALIGN, EC_ERR_NOMEM, EC_ERR_DEVICE. */
+ec_status ec_server_create(uint8_t *arena, size_t arena_bytes, const ec_serve_opts *opts, ec_server **out);
+
+/* Serve n_reqs requests to completion.  Before the clock starts, every
+ * program is copied to the device, the batches' tables are sized, and each
+ * slot budget's kernels run once on every stream (tiny launches on the
+ * arena's first bytes).  realtime = 1: request i is admitted no earlier
+ * than arrival_s after the start; 0: every request is present at once.
+ * done_s[i] receives request i's completion time on the same clock (when
+ * its slot's event was seen complete); out_offsets[i] the arena offset its
+ * outputs were placed at (the bytes stay there until a later request takes
+ * the space, or a later run's warm-up of a new slot budget writes the
+ * arena's first 4 KiB); *wall_s the run's length and *n_batches the
+ * launches made (out_offsets, wall_s and n_batches may be NULL).  Checked up front:
+ * arrival order, sizes (EC_ERR_ALIGN), and that every request fits the
+ * budget and the arena alone (EC_ERR_CAPACITY).  On a launch or device
+ * error the loop waits for the work in flight and returns the error.  One
+ * thread at a time per server. */
+ec_status ec_server_run(ec_server *server, const ec_request *reqs, int n_reqs, int realtime,
+                        ec_serve_done_fn on_done, void *user, double *done_s, size_t *out_offsets, double *wall_s,
+                        int *n_batches);
+
+/* Waits for the server's streams, then releases them, the events and the
+ * batches (not the arena). */
+void ec_server_free(ec_server *server);
 
 #ifdef __cplusplus
 }

@@ -18,6 +18,7 @@ from . import _build
 __all__ = [
     "EcError", "Program", "ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp",
     "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_device_copy", "lib",
+    "Server", "ec_server_create",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
     "SPLIT_ROWS",
@@ -58,6 +59,19 @@ class ProgramInfo(ctypes.Structure):
         "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts",
         "n_row_parts")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
+
+
+class ServeRequest(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("prog", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("block_bytes", ctypes.c_size_t)]
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int), ("max_batch", ctypes.c_int)]
+
+
+SERVE_DONE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_size_t))
 
 
 class Stripe(ctypes.Structure):
@@ -109,9 +123,16 @@ def lib():
                                      ctypes.POINTER(ctypes.c_size_t)]
         L.ec_batch_free.argtypes = [vp]
         L.ec_batch_free.restype = None
+        L.ec_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ec_server_run.argtypes = [vp, ctypes.POINTER(ServeRequest), ctypes.c_int, ctypes.c_int, SERVE_DONE_FN, vp,
+                                    dp, ctypes.POINTER(ctypes.c_size_t), dp, ctypes.POINTER(ctypes.c_int)]
+        L.ec_server_free.argtypes = [vp]
+        L.ec_server_free.restype = None
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
                      "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_program_part_bytecode", "ec_batch_build", "ec_device_copy",
-                     "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set"):
+                     "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set",
+                     "ec_server_create", "ec_server_run"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -367,3 +388,67 @@ def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
     _check(lib().ec_batch_build(arr, n, tile_bytes, _stream_handle(stream), ctypes.byref(h)),
            "ec_batch_build")
     return Batch(h.value, keep)
+
+
+class Server:
+    """Owner of an ``ec_server``: the native serving loop (``ec_server_run``)
+    over a device arena that must outlive it."""
+
+    def __init__(self, handle: int, arena):
+        self._h = ctypes.c_void_p(handle)
+        self._arena = arena
+
+    @property
+    def handle(self):
+        return self._h
+
+    def run(self, requests, realtime: bool = True, on_done=None):
+        """``requests``: list of (arrival_s, Program, input pointers,
+        block_bytes), arrivals nondecreasing.  ``on_done(ids, out_offsets)``
+        sees each completed launch (request indices, output offsets in the
+        arena) before its space is reused.  Returns (completion times in s,
+        output offsets in the arena, wall time in s, launches)."""
+        n = len(requests)
+        arr = (ServeRequest * max(1, n))()
+        flat = [p if type(p) is int else _ptr(p) for _, _, ins, _ in requests for p in ins]
+        ptrs = (ctypes.c_void_p * max(1, len(flat)))(*flat)
+        base, step, k = ctypes.addressof(ptrs), ctypes.sizeof(ctypes.c_void_p), 0
+        for i, (t, prog, ins, bb) in enumerate(requests):
+            r = arr[i]
+            r.arrival_s = t
+            r.prog = prog.handle.value
+            r.in_ = base + step * k
+            r.block_bytes = bb
+            k += len(ins)
+        done = (ctypes.c_double * max(1, n))()
+        offs = (ctypes.c_size_t * max(1, n))()
+        wall, nb = ctypes.c_double(), ctypes.c_int()
+        cb = SERVE_DONE_FN(0)
+        if on_done is not None:
+            def _cb(_user, ids, n_ids, offs):
+                on_done([ids[j] for j in range(n_ids)], [offs[j] for j in range(n_ids)])
+            cb = SERVE_DONE_FN(_cb)
+        _check(lib().ec_server_run(self._h, arr, n, 1 if realtime else 0, cb, None, done, offs, ctypes.byref(wall),
+                                   ctypes.byref(nb)), "ec_server_run")
+        return list(done)[:n], list(offs)[:n], wall.value, nb.value
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().ec_server_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ec_server_create(arena, arena_bytes: int, budget_bytes: int, n_slots: int = 4, max_batch: int = 512) -> Server:
+    """A native serving loop over the device arena ``arena`` (a tensor or a
+    pointer; ``arena_bytes`` long): ``n_slots`` streams, launches of up to
+    ``max_batch`` requests, admission within ``budget_bytes``."""
+    opts = ServeOpts(budget_bytes, n_slots, max_batch)
+    h = ctypes.c_void_p()
+    _check(lib().ec_server_create(_ptr(arena), arena_bytes, ctypes.byref(opts), ctypes.byref(h)), "ec_server_create")
+    return Server(h.value, arena)

@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import LEVEL_CO_FU_SCHED, Batch, ec_decode, ec_encode
+from . import LEVEL_CO_FU_SCHED, Batch, ec_decode, ec_encode, ec_server_create
 from .batching import ProgramCache
 
 MAX_OBJECT = 64 << 20  # largest object served (bytes)
@@ -87,10 +87,12 @@ class FirstFit:
 
 class Server:
     """Admission by HBM budget, ``n_slots`` batches in flight, each on its own
-    stream with a reusable ``ec_batch``."""
+    stream with a reusable ``ec_batch``.  ``native=True`` (default) runs the
+    loop in the library (``ec_server_run``); ``native=False`` runs the same
+    loop in Python (the methods below), kept for comparison."""
 
     def __init__(self, budget_bytes=16 << 30, n_slots=4, max_batch=512, level=LEVEL_CO_FU_SCHED, slots=38,
-                 tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True, direct_single=True):
+                 tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True, direct_single=True, native=True):
         import torch
         self.torch = torch
         self.budget = budget_bytes
@@ -105,6 +107,12 @@ class Server:
             self.cache.upload()
         self.arena = torch.empty(budget_bytes, dtype=torch.uint8, device="cuda")
         self.base = self.arena.data_ptr()
+        self.batches = 0
+        self.native = native
+        if native:
+            # streams, events, batches and their warm-up live in the library
+            self._native = ec_server_create(self.arena, budget_bytes, budget_bytes, n_slots, max_batch)
+            return
         self.heap = FirstFit(budget_bytes)
         self.slots = []
         # Work items per request: one per tile of a strip; the largest object
@@ -115,7 +123,6 @@ class Server:
             b.reserve(max_batch, max_items)  # no allocation while serving
             self.slots.append({"stream": torch.cuda.Stream(), "batch": b, "event": torch.cuda.Event(),
                                "reqs": None})
-        self.batches = 0
         self._warm(codecs)
 
     def _warm(self, codecs):
@@ -189,10 +196,13 @@ class Server:
         """Run requests (sorted by arrival) to completion; returns wall time.
         ``on_done(reqs)`` sees each finished batch while its outputs are still
         in the arena; ``realtime=False`` admits every request at once.
-        ``idle_sleep_s``: pause when nothing can be done.  The default 0 keeps
-        polling, which holds one host core; a sleep of even 20 us costs its
-        own wake-up latency twice per request (measured at 20k req/s: p50
-        0.135 ms with it, 0.071 ms polling)."""
+        ``idle_sleep_s`` (Python loop only; the native loop always polls):
+        pause when nothing can be done.  The default 0 keeps polling, which
+        holds one host core; a sleep of even 20 us costs its own wake-up
+        latency twice per request (measured at 20k req/s: p50 0.135 ms with
+        it, 0.071 ms polling).  ``t0`` (Python loop only): the clock's zero."""
+        if self.native:
+            return self._serve_native(requests, realtime, on_done)
         now_fn = (lambda: time.perf_counter() - t0)
         if t0 is None:
             t0 = time.perf_counter()
@@ -217,6 +227,26 @@ class Server:
             if idle_sleep_s > 0 and (slot is None or i >= n or requests[i].arrival > now_fn()):
                 time.sleep(idle_sleep_s)
         return now_fn()
+
+
+    def _serve_native(self, requests, realtime, on_done):
+        """The same loop in the library: the clock starts inside the call,
+        after the programs, tables and kernels are ready."""
+        reqs = [(r.arrival, self.cache.get(r.n, r.p, r.erased), r.inputs, r.block_bytes) for r in requests]
+        cb = None
+        if on_done is not None:
+            def cb(ids, offs):
+                done = [requests[i] for i in ids]
+                for r, off in zip(done, offs):
+                    r.out_off = off
+                    r.outputs = [self.base + off + j * r.block_bytes for j in range(r.n_out)]
+                on_done(done)
+        done_s, offs, wall, nb = self._native.run(reqs, realtime=realtime, on_done=cb)
+        for r, t, off in zip(requests, done_s, offs):
+            r.done = t
+            r.out_off = off
+        self.batches += nb
+        return wall
 
 
 def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool_bytes: int,
@@ -245,7 +275,7 @@ def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool
 
 
 def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=512, slots=38,
-        idle_sleep_s=0.0):
+        idle_sleep_s=0.0, native=True):
     """The serving benchmark: returns throughput and latency percentiles."""
     import torch
     pool_bytes = 1 << 30
@@ -253,7 +283,7 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     g.manual_seed(seed)
     pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
     t_setup = time.perf_counter()
-    server = Server(budget_bytes=budget_bytes, n_slots=n_slots, max_batch=max_batch, slots=slots)
+    server = Server(budget_bytes=budget_bytes, n_slots=n_slots, max_batch=max_batch, slots=slots, native=native)
     setup_s = time.perf_counter() - t_setup
     reqs = make_requests(duration_s, rate, seed, pool.data_ptr(), pool_bytes)
     torch.cuda.synchronize()
@@ -280,7 +310,8 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     finally:
         gc.enable()
     torch.cuda.synchronize()
-    res = {"requests": len(reqs), "rate_req_s": rate, "arrival_s": duration_s, "wall_s": wall,
+    res = {"loop": "native" if native else "python", "requests": len(reqs), "rate_req_s": rate,
+           "arrival_s": duration_s, "wall_s": wall,
            "GB_s": in_bytes / wall / 1e9, "in_bytes": in_bytes,
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
            "mean_ms": float(lat.mean() * 1e3), "batches": batches,

@@ -2,12 +2,15 @@
 // argument checking) run under AddressSanitizer and UndefinedBehaviorSanitizer.
 // Built with g++ from the library's C++ sources; the device launchers are
 // replaced by stubs below, and no call here reaches the HIP runtime.
+#include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
 
 #include "../../include/ec.h"
+#include "../../paper_2108_02692_amd/csrc/arena.hpp"
 #include "../../paper_2108_02692_amd/csrc/exec.hpp"
 
 namespace ec {
@@ -146,6 +149,62 @@ int main() {
     CHECK(ec_matrix_cauchy(40, 40, gen.data()) != EC_OK);
     for (int s = 0; s <= 9; ++s) CHECK(ec_status_str((ec_status)s) != nullptr);
     ec_program_free(nullptr);
+  }
+  // the serving loop's output arena: random allocations and releases never
+  // overlap, stay in range, keep live + free = size, and coalesce back to
+  // one range once everything is released
+  {
+    const size_t size = 1u << 24, align = 512;
+    ec::FirstFit heap(size, align);
+    std::vector<std::pair<size_t, size_t>> live;
+    uint64_t x = 12345;
+    auto rnd = [&x]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+    for (int it = 0; it < 4000; ++it) {
+      if (!live.empty() && rnd() % 100 < 45) {
+        const size_t k = rnd() % live.size();
+        heap.release(live[k].first, live[k].second);
+        live.erase(live.begin() + (long)k);
+      } else {
+        size_t got = 0;
+        const size_t want = 1 + rnd() % 200000;
+        const size_t off = heap.alloc(want, &got);
+        if (off != SIZE_MAX) {
+          CHECK(got >= want && got % align == 0 && off % align == 0 && off + got <= size);
+          live.push_back({off, got});
+        }
+      }
+      std::vector<std::pair<size_t, size_t>> spans(live);
+      std::sort(spans.begin(), spans.end());
+      for (size_t k = 1; k < spans.size(); ++k) CHECK(spans[k - 1].first + spans[k - 1].second <= spans[k].first);
+      size_t total = 0;
+      for (auto &sp : spans) total += sp.second;
+      for (auto &fr : heap.free_ranges()) total += fr.second;
+      CHECK(total == size);
+    }
+    for (auto &sp : live) heap.release(sp.first, sp.second);
+    CHECK(heap.free_ranges().size() == 1 && heap.free_ranges().begin()->second == size);
+    size_t got = 0;
+    CHECK(heap.alloc(size + 1, &got) == SIZE_MAX);
+  }
+  // the server's argument checks (made before any HIP call)
+  {
+    ec_server *sv = nullptr;
+    ec_serve_opts o{1u << 20, 2, 4};
+    std::vector<uint8_t> host(1 << 16);
+    CHECK(ec_server_create(nullptr, 1 << 20, &o, &sv) == EC_ERR_ARG && sv == nullptr);
+    CHECK(ec_server_create(host.data(), host.size(), nullptr, &sv) == EC_ERR_ARG);
+    CHECK(ec_server_create(host.data(), host.size(), &o, nullptr) == EC_ERR_ARG);
+    o.n_slots = 17;
+    CHECK(ec_server_create(host.data(), host.size(), &o, &sv) == EC_ERR_ARG);
+    o.n_slots = 2;
+    o.max_batch = 0;
+    CHECK(ec_server_create(host.data(), host.size(), &o, &sv) == EC_ERR_ARG);
+    o.max_batch = 4;
+    CHECK(ec_server_create(host.data() + 1, host.size() - 1, &o, &sv) == EC_ERR_ALIGN);
+    CHECK(ec_server_create(host.data(), 1024, &o, &sv) == EC_ERR_ARG);
+    double done = 0;
+    CHECK(ec_server_run(nullptr, nullptr, 0, 1, nullptr, nullptr, &done, nullptr, nullptr, nullptr) == EC_ERR_ARG);
+    ec_server_free(nullptr);
   }
   std::printf("lib_driver: %d programs compiled and inspected, %d check failures\n", compiled, failures);
   return failures == 0 ? 0 : 1;

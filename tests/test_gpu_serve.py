@@ -27,7 +27,8 @@ def expected(server, req, pool_h, pool_ptr):
     return oracle.apply(D, [np.ascontiguousarray(b) for b in ins])
 
 
-def test_mix_equals_alone_equals_oracle():
+@pytest.mark.parametrize("native", [True, False])
+def test_mix_equals_alone_equals_oracle(native):
     pool_bytes = 8 << 20
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
@@ -38,7 +39,7 @@ def test_mix_equals_alone_equals_oracle():
     assert len(reqs) > 40
     # A budget far below the total forces admission back-pressure and many
     # batches in flight; small batches interleave codecs and sizes.
-    server = SV.Server(budget_bytes=16 << 20, n_slots=3, max_batch=7, warm=False)
+    server = SV.Server(budget_bytes=16 << 20, n_slots=3, max_batch=7, warm=False, native=native)
     for r in reqs:
         server.cache.get(r.n, r.p, r.erased)
     for r in reqs:
@@ -51,6 +52,7 @@ def test_mix_equals_alone_equals_oracle():
     torch.cuda.synchronize()
     assert all(r.done >= 0 for r in reqs) and len(mixed) == len(reqs)
     assert server.batches >= len(reqs) // 7 and server.used == 0
+    assert len({r.out_off for r in reqs}) > 1  # the arena's space was reused across batches
     mixed = [mixed[r.rid] for r in reqs]
     alone = []
     for r in reqs:
@@ -64,3 +66,42 @@ def test_mix_equals_alone_equals_oracle():
         want = expected(server, reqs[k], pool_h, pool.data_ptr())
         for j in range(reqs[k].n_out):
             assert np.array_equal(alone[k][j], want[j]), "oracle: request %d output %d" % (k, j)
+
+
+def test_native_loop_realtime_and_argument_errors():
+    """The library's loop on a short Poisson stream in real time: every
+    request completes after its arrival and equals the oracle; requests out
+    of arrival order or larger than the budget are refused before any
+    launch."""
+    pool_bytes = 8 << 20
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12)
+    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    pool_h = pool.cpu().numpy()
+    reqs = SV.make_requests(0.01, 20000.0, seed=6, pool_ptr=pool.data_ptr(), pool_bytes=pool_bytes, hi=1 << 20)
+    server = SV.Server(budget_bytes=64 << 20, n_slots=4, max_batch=16, warm=False)
+    got = {}
+
+    def grab(done):
+        got.update({r.rid: o for r, o in zip(done, outputs_of(server, done))})
+    wall = server.serve(reqs, on_done=grab)
+    torch.cuda.synchronize()
+    assert len(got) == len(reqs) and wall >= reqs[-1].arrival
+    assert all(r.done >= r.arrival for r in reqs)
+    for k in range(0, len(reqs), 7):
+        want = expected(server, reqs[k], pool_h, pool.data_ptr())
+        for j in range(reqs[k].n_out):
+            assert np.array_equal(got[reqs[k].rid][j], want[j]), "request %d output %d" % (k, j)
+    from paper_2108_02692_amd import EcError
+    a, b = reqs[0], reqs[1]
+    a.arrival, b.arrival = 0.002, 0.001
+    with pytest.raises(EcError) as e:
+        server.serve([a, b])  # arrivals out of order
+    assert e.value.name == "EC_ERR_ARG"
+    small = SV.Server(budget_bytes=256 << 10, n_slots=2, max_batch=4, warm=False)
+    big = max(reqs, key=lambda r: r.bytes)
+    big.arrival = 0.0
+    assert big.bytes > 256 << 10
+    with pytest.raises(EcError) as e:
+        small.serve([big])
+    assert e.value.name == "EC_ERR_CAPACITY"
