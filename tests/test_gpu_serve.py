@@ -105,3 +105,49 @@ def test_native_loop_realtime_and_argument_errors():
     with pytest.raises(EcError) as e:
         small.serve([big])
     assert e.value.name == "EC_ERR_CAPACITY"
+
+
+def test_native_loop_mixed_slot_budgets():
+    """Requests whose programs use different slot budgets (one kernel
+    instance per launch) interleaved in one run, all present at once: the
+    loop splits its batches at each change of budget, warms each budget's
+    kernels, and every output equals the oracle."""
+    import paper_2108_02692_amd as E
+    rng = np.random.default_rng(21)
+    pool_bytes = 4 << 20
+    pool_h = rng.integers(0, 256, pool_bytes, dtype=np.uint8)
+    pool = torch.from_numpy(pool_h).cuda()
+    arena = torch.empty(32 << 20, dtype=torch.uint8, device="cuda")
+    codecs = [(10, 4, (), 38), (4, 2, (), 24), (6, 3, (1, 7), 32), (10, 4, (2, 4, 5, 11), 38)]
+    progs = {c: E.ec_compile_slp(c[0], c[1], E.ec_matrix_cauchy(c[0], c[1]), list(c[2]), slot_budget=c[3])
+             for c in codecs}
+    reqs, meta = [], []
+    for k in range(40):
+        c = codecs[k % len(codecs)] if k % 5 else codecs[1]
+        prog = progs[c]
+        bb = 512 * int(rng.integers(1, 80))
+        offs = (rng.integers(0, (pool_bytes - bb) // 512, len(prog.in_blocks)) * 512).tolist()
+        reqs.append((0.0, prog, [pool.data_ptr() + o for o in offs], bb))
+        meta.append((c, offs, bb))
+    srv = E.ec_server_create(arena, arena.numel(), budget_bytes=16 << 20, n_slots=3, max_batch=8)
+    got = {}
+
+    def grab(ids, out_offs):
+        for i, off in zip(ids, out_offs):
+            c, _, bb = meta[i]
+            got[i] = arena[off: off + len(progs[c].out_blocks) * bb].cpu().numpy().copy()
+    done, offs, wall, nb = srv.run(reqs, realtime=False, on_done=grab)
+    torch.cuda.synchronize()
+    assert len(got) == len(reqs) and all(t >= 0 for t in done) and nb >= 10
+    for i, (c, ins, bb) in enumerate(meta):
+        n, p, er, _ = c
+        G = np.array(E.ec_matrix_cauchy(n, p), dtype=np.uint8)
+        data = [pool_h[o: o + bb] for o in ins]
+        if er:
+            D, surv = oracle.decode_matrix(G, n, p, list(er))
+            assert surv == progs[c].in_blocks
+        else:
+            D = G[n:]
+        want = np.concatenate(oracle.apply(D, [np.ascontiguousarray(b) for b in data]))
+        assert np.array_equal(got[i], want), "request %d %s" % (i, c)
+    srv.free()
