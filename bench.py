@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--batch-stripes", type=int, default=8192, help="stripes in the batched workload (0 = skip)")
     ap.add_argument("--batch-max-mib", type=int, default=4, help="largest block of the batched workload (MiB)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of Poisson arrivals (0 = skip)")
+    ap.add_argument("--serve-runs", type=int, default=3,
+                    help="serving runs of the same arrival stream, each with its own server; the latency and "
+                         "drain figures are their medians (every run's in 'runs')")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--decode-all-slots", type=int, default=44, help="slot budget of the every-erasure-set decode")
     ap.add_argument("--sweep", action="store_true",
@@ -155,8 +158,7 @@ def main():
               flush=True)
         return
     if args.only == "serve":
-        from paper_2108_02692_amd import serve
-        print(json.dumps({"serving": serve.run(duration_s=args.serve_seconds, seed=7)}), flush=True)
+        print(json.dumps({"serving": bench_serving(args)}), flush=True)
         return
     n, p = 10, 4
     S = args.block_mib << 20
@@ -297,9 +299,8 @@ def main():
         log("batched: %.3f ms" % out["batched"]["ms"])
         torch.cuda.empty_cache()
     if args.only == "all" and args.serve_seconds > 0:
-        from paper_2108_02692_amd import serve
         log("serving ...")
-        out["serving"] = serve.run(duration_s=args.serve_seconds, seed=7)
+        out["serving"] = bench_serving(args)
         log("serving: p50 %.3f ms p99 %.3f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]))
         torch.cuda.empty_cache()
     if not args.no_cpu:
@@ -386,6 +387,20 @@ def bench_small(args, stream):
         ms = time_launches(lambda: E.ec_encode(prog, data, parity, S, stream), max(args.steps, 100),
                            args.warmup, stream)
         res[tag] = {"ms": ms, "GB_s": n * S / ms / 1e6}
+    return res
+
+
+def bench_serving(args):
+    """The serving loop on 20k req/s Poisson arrivals, ``--serve-runs`` times
+    (the host can interrupt the loop's thread, which moves p99 from run to
+    run): medians of the latency and drain figures, every run's in 'runs'."""
+    import numpy as np
+    from paper_2108_02692_amd import serve
+    runs = [serve.run(duration_s=args.serve_seconds, seed=7) for _ in range(max(1, args.serve_runs))]
+    res = dict(runs[0])
+    for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s"):
+        res[k] = float(np.median([r[k] for r in runs]))
+    res["runs"] = [{k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s")} for r in runs]
     return res
 
 
