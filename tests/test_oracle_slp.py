@@ -103,6 +103,31 @@ def test_P0_optimality_bruteforce():
     assert shortest_xor_count(P0, 4, 5, disjoint_only=True) == G_P0["shortest_xors_without_cancellation"]
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_xorrepair_bounded_by_bruteforce_on_tiny_instances(seed):
+    """Random targets over 4 constants: XorRePair's program computes every
+    target, and its XOR count lies between the shortest program found by
+    exhaustive search (Sec. 4: the shortest-SLP problem it approximates) and
+    the plain count; RePair, which cannot cancel, is never shorter than the
+    shortest program without cancellation."""
+    rng = random.Random(seed)
+    targets = []
+    while len(targets) < rng.randint(2, 4):
+        t = rng.randint(1, 15)
+        if bin(t).count("1") >= 2 and t not in targets:
+            targets.append(t)
+    plain = sum(bin(t).count("1") - 1 for t in targets)
+    comp = S.repair(targets, 4, xor_rebuild=True)
+    assert eval_comp(comp) == targets
+    n_x = len(comp.temps)
+    best = shortest_xor_count(targets, 4, plain)
+    assert best is not None and best <= n_x <= plain, (targets, best, n_x, plain)
+    rp = S.repair(targets, 4, xor_rebuild=False)
+    assert eval_comp(rp) == targets
+    best_disjoint = shortest_xor_count(targets, 4, plain, disjoint_only=True)
+    assert best_disjoint <= len(rp.temps) <= plain, (targets, best_disjoint, len(rp.temps))
+
+
 def test_intro_example_compress_and_fuse():
     gx = golden("intro_example")
     rows = [letters_to_bits(gx["program"][v], gx["constants"]) for v in ("nu1", "nu2", "nu3")]
