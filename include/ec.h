@@ -299,8 +299,9 @@ void ec_batch_free(ec_batch *batch);
  * the programs above.  ec_server_run admits arrived requests, in arrival
  * order, while their input + output bytes fit budget_bytes (counting every
  * request in flight) and their outputs fit a first-fit arena in the
- * caller's device buffer; packs the admitted requests (up to max_batch, of
- * one slot budget) into one launch on a free slot's stream, a plain
+ * caller's device buffer; spreads the arrived requests over the free slots
+ * and packs each slot's share (up to max_batch, of one slot budget) into one
+ * launch on that slot's stream, a plain
  * ec_encode / ec_decode launch for one request and a reusable ec_batch for
  * more; and keeps admitting while earlier launches run, so requests
  * admitted meanwhile overlap with them on the device.  Completion is found

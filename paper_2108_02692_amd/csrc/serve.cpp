@@ -245,14 +245,25 @@ ec_status ec_server_run(ec_server *sv, const ec_request *reqs, int n_reqs, int r
   while (finished < n) {
     if ((err = retire()) != EC_OK) break;
     ec_server::Slot *slot = nullptr;
+    size_t n_free = 0;
     for (auto &s : sv->slots)
-      if (s.reqs.empty()) { slot = &s; break; }
+      if (s.reqs.empty()) {
+        if (!slot) slot = &s;
+        ++n_free;
+      }
     if (!slot || next >= n) continue;
     const double now = realtime ? now_s() - t0 : INFINITY;
-    // Arrived requests that fit, up to max_batch, all of one slot budget
-    // (one kernel instance per batch).
+    // Arrived requests spread over the free slots (a request launched alone
+    // on its own stream finishes sooner than in a batch with others), each
+    // launch taking up to max_batch of them.
+    size_t arrived = 0;
+    const size_t cap = n_free * (size_t)sv->max_batch;
+    while (next + arrived < n && reqs[next + arrived].arrival_s <= now && arrived < cap) ++arrived;
+    const size_t take = std::min<size_t>((size_t)sv->max_batch, (arrived + n_free - 1) / n_free);
+    // Arrived requests that fit, up to `take`, all of one slot budget (one
+    // kernel instance per batch).
     int kslots = -1;
-    while (next < n && reqs[next].arrival_s <= now && (int)slot->reqs.size() < sv->max_batch) {
+    while (next < n && reqs[next].arrival_s <= now && slot->reqs.size() < take) {
       const ec_request &q = reqs[next];
       if (kslots >= 0 && q.prog->slots != kslots) break;
       if (used + bytes_of(next) > sv->budget) break;
