@@ -3,11 +3,12 @@
 //
 // Requests arrive on the caller's clock (arrival times relative to the start
 // of a run).  The loop admits arrived requests while their inputs and
-// outputs fit the budget and their outputs fit a first-fit arena, packs them
-// into one launch on a free slot's stream (a plain launch for a single
-// request, a reusable batch otherwise), and keeps admitting while earlier
-// launches run, so work admitted meanwhile overlaps on the device.  It polls
-// each busy slot's event and records completion times on the same clock.
+// outputs fit the budget and their outputs fit a first-fit arena, spreads
+// them over the free slots and packs each slot's share into one launch on
+// that slot's stream (a plain launch for a single request, a reusable batch
+// otherwise), and keeps admitting while earlier launches run, so work
+// admitted meanwhile overlaps on the device.  It polls each busy slot's
+// event and records completion times on the same clock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
