@@ -93,11 +93,13 @@ typedef struct {
 /* Row split.  Unless compiled with EC_SPLIT_NEVER, a program also carries
  * "parts": independent programs that each compute some of the output rows
  * from the inputs they need (scheduled from the plain bitmatrix rows, which
- * make the shortest chains of records, whatever the level), in two sets:
+ * make the shortest chains of records, whatever the level), in three sets:
  *  - block parts: up to 8, each a group of whole output blocks (only when
  *    there is more than one output block);
  *  - row parts: up to 32, each one bit row (beyond 4 output blocks, runs
- *    of floor or ceil(8 n_out / 32) consecutive rows).
+ *    of floor or ceil(8 n_out / 32) consecutive rows);
+ *  - pair parts: up to 16, each two consecutive bit rows (beyond 4 output
+ *    blocks, runs of floor or ceil(8 n_out / 32) pairs).
  * A launch over a stripe with few tiles then runs one wave per (tile, part)
  * instead of one per tile, which gives short stripes more waves and each
  * wave a shorter chain of records and a deeper load ring, at the cost of
@@ -105,12 +107,14 @@ typedef struct {
  * A batch (ec_batch_*) decides for all its EC_SPLIT_AUTO stripes at once,
  * by the same rule over the work items of the whole batch. */
 enum {
-  EC_SPLIT_AUTO = 0,   /* row parts when one wave per (tile, row part) fits in the waves the
-                          chip keeps resident for the program's slot budget, else block
-                          parts when one wave per (tile, block part) does (default) */
+  EC_SPLIT_AUTO = 0,   /* the finest set that fits, none if no set does (default): row parts,
+                          then pair parts, while one wave per (tile, part) leaves at most two
+                          waves per SIMD; block parts while those waves fit in the waves the
+                          chip keeps resident for the program's slot budget */
   EC_SPLIT_NEVER = 1,  /* one wave per tile; no parts are built */
   EC_SPLIT_ALWAYS = 2, /* block parts on every launch when the program has them */
-  EC_SPLIT_ROWS = 3    /* row parts on every launch when the program has them */
+  EC_SPLIT_ROWS = 3,   /* row parts on every launch when the program has them */
+  EC_SPLIT_PAIRS = 4   /* pair parts on every launch when the program has them */
 };
 
 typedef struct {
@@ -133,6 +137,7 @@ typedef struct {
   uint32_t n_words;     /* bytecode words */
   uint32_t n_parts;     /* block parts for the row split (0: none, e.g. one output block) */
   uint32_t n_row_parts; /* row parts for the row split (0: none) */
+  uint32_t n_pair_parts; /* pair parts for the row split (0: none) */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
 } ec_program_info;
@@ -233,7 +238,8 @@ ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, si
 
 /* The bytecode of part `part` of a program: block part `part` for
  * 0 <= part < info.n_parts, then row part `part - n_parts` for
- * part < n_parts + n_row_parts (host copy; same record format as
+ * part < n_parts + n_row_parts, then pair part `part - n_parts -
+ * n_row_parts` up to n_parts + n_row_parts + n_pair_parts (host copy; same record format as
  * ec_program_bytecode, storing only the part's output rows).  EC_ERR_ARG for
  * a part that does not exist. */
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words);

@@ -145,7 +145,7 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   std::vector<std::pair<uintptr_t, uintptr_t>> reads, writes;
   int slots = 0;
   size_t in_bytes = 0, out_bytes = 0;
-  uint64_t items_rows = 0, items_blocks = 0;  // work items with row parts, with block parts
+  uint64_t items_rows = 0, items_pairs = 0, items_blocks = 0;  // work items with each set of parts
   for (int s = 0; s < n_stripes; ++s) {
     const ec_stripe &st = stripes[s];
     const ec_program *prog = st.prog;
@@ -175,24 +175,29 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
     d.strip_len = (uint32_t)(st.block_bytes / 8);
     const uint64_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
     items_rows += n_tiles * std::max<size_t>(1, prog->row_parts.size());
+    items_pairs += n_tiles * std::max<size_t>(1, prog->pair_parts.size());
     items_blocks += n_tiles * std::max<size_t>(1, prog->parts.size());
     in_bytes += (size_t)n_in * st.block_bytes;
     out_bytes += (size_t)n_out * st.block_bytes;
   }
   // Row split as for one stripe, decided for the whole batch: row parts
-  // when one wave per (tile, row part) of every stripe fits in one round of
-  // resident waves, else block parts when one wave per (tile, block part)
-  // does, else none (stripes compiled with EC_SPLIT_ROWS / ALWAYS / NEVER
-  // take their own choice).
+  // when one wave per (tile, row part) of every stripe leaves at most two
+  // waves per SIMD, else pair parts when theirs do, else block parts when
+  // all theirs are resident, else none (stripes compiled with another
+  // policy than EC_SPLIT_AUTO take their own choice).
   const uint64_t resident_waves = 4ull * (uint64_t)b->n_cus * waves_per_simd(slots);
-  const bool rows_fit = items_rows <= resident_waves;
-  const bool blocks_fit = !rows_fit && items_blocks <= resident_waves;
+  const uint64_t fine_waves = 2ull * 4 * (uint64_t)b->n_cus;  // two waves per SIMD
+  const bool rows_fit = items_rows <= fine_waves;
+  const bool pairs_fit = !rows_fit && items_pairs <= fine_waves;
+  const bool blocks_fit = !rows_fit && !pairs_fit && items_blocks <= resident_waves;
   for (int s = 0; s < n_stripes; ++s) {
     const ec_program *prog = stripes[s].prog;
     StripeDesc &d = desc[s];
     const std::vector<uint32_t> *off = nullptr;
     if (prog->split == EC_SPLIT_ROWS || (prog->split == EC_SPLIT_AUTO && rows_fit))
       off = prog->row_parts.empty() ? nullptr : &prog->row_part_off;
+    else if (prog->split == EC_SPLIT_PAIRS || (prog->split == EC_SPLIT_AUTO && pairs_fit))
+      off = prog->pair_parts.empty() ? nullptr : &prog->pair_part_off;
     else if (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && blocks_fit))
       off = prog->parts.empty() ? nullptr : &prog->part_off;
     const uint32_t n_parts = off ? (uint32_t)off->size() : 1u;

@@ -107,8 +107,8 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   if (n_cus <= 0) return EC_ERR_DEVICE;
   const uint64_t resident = (uint64_t)n_cus * waves_per_simd(prog->slots);  // workgroups of 4 waves
   // Row split for short stripes, when one wave per (tile, part) still fits
-  // in one round of resident waves: single-row parts first, else parts of
-  // whole output blocks.  Measured on RS(10,4) encodes (32 row parts or 4
+  // in one round of resident waves: single-row parts first, else pairs of
+  // rows, else parts of whole output blocks.  Measured on RS(10,4) encodes (32 row parts or 4
   // block parts against one wave per tile): 8 KiB - 256 KiB blocks 12.0 -
   // 12.3 us with row parts, 22.5 - 23.0 us with block parts, 28.5 - 30.5 us
   // unsplit; 1 MiB 25.7 us with row parts forced, 23.3 us with block parts;
@@ -119,13 +119,20 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   a.part_off[0] = 0;
   const uint64_t waves = 4 * resident;
   const std::vector<uint32_t> *off = nullptr;
-  const uint64_t nb = prog->parts.size(), nr = prog->row_parts.size();
+  const uint64_t nb = prog->parts.size(), nr = prog->row_parts.size(), np = prog->pair_parts.size();
   if (prog->split == EC_SPLIT_ROWS) {
     if (nr) off = &prog->row_part_off;
+  } else if (prog->split == EC_SPLIT_PAIRS) {
+    if (np) off = &prog->pair_part_off;
   } else if (prog->split == EC_SPLIT_ALWAYS) {
     if (nb) off = &prog->part_off;
   } else if (prog->split == EC_SPLIT_AUTO) {
-    if (nr && a.n_tiles * nr <= waves) off = &prog->row_part_off;
+    // The finest set that fits: row or pair parts while there are at most
+    // two waves per SIMD (their chains run side by side), block parts while
+    // all their waves are resident.
+    const uint64_t fine = 2ull * 4 * (uint64_t)n_cus;
+    if (nr && a.n_tiles * nr <= fine) off = &prog->row_part_off;
+    else if (np && a.n_tiles * np <= fine) off = &prog->pair_part_off;
     else if (nb && a.n_tiles * nb <= waves) off = &prog->part_off;
   }
   if (off) {
@@ -181,7 +188,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
-  if (o.split > EC_SPLIT_ROWS) return EC_ERR_UNSUPPORTED;
+  if (o.split > EC_SPLIT_PAIRS) return EC_ERR_UNSUPPORTED;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -286,7 +293,9 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   //  * single bit rows, or runs of floor or ceil(rows / kMaxRowParts) rows
   //    beyond 4 output blocks (at most kMaxRowParts): the shortest stripes,
   //    where a wave's time is its chain of records and a single row needs
-  //    only about half the inputs.
+  //    only about half the inputs;
+  //  * pairs of rows, or runs of pairs beyond 4 output blocks (at most
+  //    kMaxRowParts / 2): stripes a little too long for single rows.
   // Parts run where a lone wave's chain of records is the time, and there
   // the plain rows win whatever the level: one record per input strip and
   // no records for temporaries (measured on RS(10,4) encodes, 8 KiB - 1 MiB
@@ -297,6 +306,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   prog->image = prog->code.words;
   prog->part_off.clear();
   prog->row_part_off.clear();
+  prog->pair_part_off.clear();
   const int n_rows = 8 * n_out;
   // Groups of whole units of `unit` rows; consecutive groups differ by at
   // most one unit and together cover every row.
@@ -322,6 +332,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (o.split != EC_SPLIT_NEVER) {
     if (n_out > 1 && !build_parts(8, kMaxParts, prog->parts)) return EC_ERR_UNSUPPORTED;
     if (n_rows > 1 && !build_parts(1, kMaxRowParts, prog->row_parts)) return EC_ERR_UNSUPPORTED;
+    if (n_rows > 2 && !build_parts(2, kMaxRowParts / 2, prog->pair_parts)) return EC_ERR_UNSUPPORTED;
   }
   for (const PushCode &part : prog->parts) {
     prog->part_off.push_back((uint32_t)prog->image.size());
@@ -329,6 +340,10 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   }
   for (const PushCode &part : prog->row_parts) {
     prog->row_part_off.push_back((uint32_t)prog->image.size());
+    prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
+  }
+  for (const PushCode &part : prog->pair_parts) {
+    prog->pair_part_off.push_back((uint32_t)prog->image.size());
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
@@ -354,6 +369,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_words = (uint32_t)prog->code.words.size();
   info.n_parts = (uint32_t)prog->parts.size();
   info.n_row_parts = (uint32_t)prog->row_parts.size();
+  info.n_pair_parts = (uint32_t)prog->pair_parts.size();
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -446,8 +462,10 @@ ec_status ec_program_upload(ec_program *prog) {
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words) {
   if (!prog || !words || !n_words || part < 0) return EC_ERR_ARG;
   const int nb = (int)prog->parts.size();
-  if (part >= nb + (int)prog->row_parts.size()) return EC_ERR_ARG;
-  const PushCode &c = part < nb ? prog->parts[part] : prog->row_parts[part - nb];
+  const int nr = (int)prog->row_parts.size();
+  if (part >= nb + nr + (int)prog->pair_parts.size()) return EC_ERR_ARG;
+  const PushCode &c = part < nb ? prog->parts[part]
+                      : part < nb + nr ? prog->row_parts[part - nb] : prog->pair_parts[part - nb - nr];
   *words = c.words.data();
   *n_words = c.words.size();
   return EC_OK;

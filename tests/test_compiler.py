@@ -258,7 +258,7 @@ def test_compile_errors():
         E.ec_compile_slp(10, 4, gen, block_strips=81)
     assert e.value.name == "EC_ERR_ARG"
     with pytest.raises(E.EcError) as e:
-        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_ROWS + 1)
+        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_PAIRS + 1)
     assert e.value.name == "EC_ERR_UNSUPPORTED"
     with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
@@ -271,32 +271,36 @@ def test_compile_errors():
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
 def test_row_split_parts_cover_the_rows(n, p, er, level):
     """Every row-split part, run by the independent simulator, stores only its
-    own output rows; the block parts together, and the row parts together,
-    store every output strip with the bitmatrix row's value, exactly once."""
+    own output rows; each set of parts (blocks, single rows, pairs of rows)
+    stores every output strip with the bitmatrix row's value, exactly once."""
     gen = E.ec_matrix_cauchy(n, p)
     rows = oracle_rows(gen, n, p, er)
     prog = E.ec_compile_slp(n, p, gen, er, level=level)
     n_out = len(prog.out_blocks)
-    n_parts, n_row_parts = prog.info["n_parts"], prog.info["n_row_parts"]
-    assert n_parts == (min(n_out, 8) if n_out > 1 else 0) or n_parts == 0
-    assert n_row_parts == min(8 * n_out, 32) or n_row_parts == 0
-    lo_rows, hi_rows = 8 * n_out // 32, -(-8 * n_out // 32)  # rows per row part
-    for lo, hi, whole_blocks in ((0, n_parts, True), (n_parts, n_parts + n_row_parts, False)):
+    nb, nr, npair = prog.info["n_parts"], prog.info["n_row_parts"], prog.info["n_pair_parts"]
+    assert nb == (min(n_out, 8) if n_out > 1 else 0) or nb == 0
+    assert nr == min(8 * n_out, 32) or nr == 0
+    assert npair == min(4 * n_out, 16) or npair == 0
+
+    def sizes(unit, groups):  # rows per part of a set of runs of `unit` rows
+        units = 8 * n_out // unit
+        return {unit * (units // groups), unit * -(-units // groups)} - {0}
+    for lo, hi, kind in ((0, nb, "block"), (nb, nb + nr, "row"), (nb + nr, nb + nr + npair, "pair")):
         got = {}
         for q in range(lo, hi):
             part = simulate(prog.part_bytecode(q), prog.info["slots"], len(prog.in_blocks), n_out)
             assert part and not set(part) & set(got)
-            if whole_blocks:
+            if kind == "block":
                 assert all(8 * (o // 8) + j in part for o in part for j in range(8))
             else:  # a run of rows right after the previous part's, of even size
                 assert sorted(part) == list(range(len(got), len(got) + len(part)))
-                assert len(part) in (max(1, lo_rows), hi_rows)
+                assert len(part) in sizes(1 if kind == "row" else 2, hi - lo), (kind, len(part))
             got.update(part)
         if hi > lo:
             assert [got[o] for o in range(len(rows))] == rows
     info = E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_NEVER).info
-    assert info["n_parts"] == 0 and info["n_row_parts"] == 0
+    assert info["n_parts"] == 0 and info["n_row_parts"] == 0 and info["n_pair_parts"] == 0
     with pytest.raises(E.EcError):
-        prog.part_bytecode(n_parts + n_row_parts)
+        prog.part_bytecode(nb + nr + npair)
     with pytest.raises(E.EcError):
         prog.part_bytecode(-1)

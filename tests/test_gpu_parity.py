@@ -371,7 +371,7 @@ def test_launch_argument_errors():
 @pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, ()), (14, 4, (0, 13)), (2, 1, ()),
                                     (4, 12, ()), (2, 10, ()), (4, 12, tuple(range(1, 12)))])
 def test_row_split_matches_oracle(n, p, er):
-    """Short stripes run one wave per (tile, part): row parts and block parts
+    """Short stripes run one wave per (tile, part): row, pair and block parts
     forced, the split off and left to the library, on ragged and small block
     sizes, equal the oracle."""
     gen = E.ec_matrix_cauchy(n, p)
@@ -380,7 +380,7 @@ def test_row_split_matches_oracle(n, p, er):
         data = W.host_blocks(n, S, seed=S % 1000 + n)
         blocks = data + oracle.encode(G, n, p, data)
         want = [blocks[e] for e in er] if er else blocks[n:]
-        for split in (E.SPLIT_ROWS, E.SPLIT_ALWAYS, E.SPLIT_NEVER, E.SPLIT_AUTO):
+        for split in (E.SPLIT_ROWS, E.SPLIT_PAIRS, E.SPLIT_ALWAYS, E.SPLIT_NEVER, E.SPLIT_AUTO):
             prog = E.ec_compile_slp(n, p, gen, list(er), split=split)
             got = run_decode(prog, blocks, S) if er else run_encode(prog, data, S)
             assert_blocks_equal(got, want, "RS(%d,%d) %s S=%d split %d" % (n, p, er, S, split))
@@ -393,7 +393,7 @@ def test_random_cases_match_oracle():
     rng = random.Random(2024)
     budgets = (0, 24, 32, 36, 38, 40, 44, 48)
     levels = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED)
-    splits = (E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS, E.SPLIT_ROWS)
+    splits = (E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS, E.SPLIT_ROWS, E.SPLIT_PAIRS)
     done = 0
     while done < 40:
         n = rng.randint(1, 20)
