@@ -106,15 +106,14 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   const int n_cus = device_cus();
   if (n_cus <= 0) return EC_ERR_DEVICE;
   const uint64_t resident = (uint64_t)n_cus * waves_per_simd(prog->slots);  // workgroups of 4 waves
-  // Row split for short stripes, when one wave per (tile, part) still fits
-  // in one round of resident waves: single-row parts first, else pairs of
-  // rows, else parts of whole output blocks.  Measured on RS(10,4) encodes (32 row parts or 4
-  // block parts against one wave per tile): 8 KiB - 256 KiB blocks 12.0 -
-  // 12.3 us with row parts, 22.5 - 23.0 us with block parts, 28.5 - 30.5 us
-  // unsplit; 1 MiB 25.7 us with row parts forced, 23.3 us with block parts;
-  // 8 MiB 47 us with block parts forced against 32 us unsplit: every part
-  // reads its inputs, so once the waves are busy anyway a split only adds
-  // work.
+  // Row split for short stripes: single-row parts first, else pairs of
+  // rows, else parts of whole output blocks.  Measured on RS(10,4) encodes
+  // (32 row parts, 16 pair parts or 4 block parts against one wave per
+  // tile): 8 KiB - 256 KiB blocks 10.5 - 10.8 us with row parts, 20.2 - 20.7
+  // us with block parts, 28.5 - 30.3 us unsplit; 1 MiB 18.0 us with pair
+  // parts, 20.9 us with block parts, 23.7 us with row parts; 8 MiB 47 us
+  // with block parts forced against 32 us unsplit: every part reads its
+  // inputs, so once the waves are busy anyway a split only adds work.
   a.n_parts = 1;
   a.part_off[0] = 0;
   const uint64_t waves = 4 * resident;
