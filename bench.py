@@ -410,24 +410,10 @@ def bench_batched(args, stream):
     uniformly drawn erasure sets; one persistent graph launch per step.
     Inputs are slices of one seeded random pool (read-only, so stripes may
     share bytes); every output is its own buffer."""
-    import numpy as np
-    import torch
     from paper_2108_02692_amd import autotune, batching
 
-    specs = batching.mixed_specs(args.batch_stripes, seed=4, hi=args.batch_max_mib << 20)
-    pool_bytes = 4 << 30
-    g = torch.Generator(device="cuda")
-    g.manual_seed(4)
-    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
-    rng = np.random.default_rng(5)
-    out_total = sum(s.n_out * s.block_bytes for s in specs)
-    out_buf = torch.empty(out_total, dtype=torch.uint8, device="cuda")
-    inputs, outputs, off = [], [], 0
-    for s in specs:
-        hi = (pool_bytes - s.block_bytes) // 4096
-        inputs.append([pool[o:o + s.block_bytes] for o in (rng.integers(0, hi, s.n_in) * 4096).tolist()])
-        outputs.append([out_buf[off + j * s.block_bytes: off + (j + 1) * s.block_bytes] for j in range(s.n_out)])
-        off += s.n_out * s.block_bytes
+    specs, pool, inputs, outputs, out_buf = batching.mixed_workload(args.batch_stripes, hi=args.batch_max_mib << 20)
+    out_total = out_buf.numel()
     in_bytes = sum(s.n_in * s.block_bytes for s in specs)
     key = "mix4-%d-%dMiB" % (args.batch_stripes, args.batch_max_mib)
     best, table = autotune.tune(key, specs, inputs, outputs, stream, retune=args.retune,

@@ -60,6 +60,8 @@ def lib():
             L.oracle_bitmatrix.restype = None
             L.oracle_bitmatrix.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p]
             L.oracle_apply.argtypes = [ctypes.c_int, ctypes.c_int, u8p, pp, pp, ctypes.c_size_t]
+            L.oracle_apply_range.argtypes = [ctypes.c_int, ctypes.c_int, u8p, pp, pp, ctypes.c_size_t,
+                                             ctypes.c_size_t, ctypes.c_size_t]
             L.oracle_encode.argtypes = [ctypes.c_int, ctypes.c_int, u8p, pp, pp, ctypes.c_size_t]
             L.oracle_decode_matrix.argtypes = [ctypes.c_int, ctypes.c_int, u8p, ip, ctypes.c_int, u8p, ip]
             L.oracle_decode.argtypes = [ctypes.c_int, ctypes.c_int, u8p, ip, ctypes.c_int, pp, pp, ctypes.c_size_t]
@@ -162,35 +164,68 @@ def decode_matrix(gen: np.ndarray, n: int, p: int, erased):
 
 
 # ---------------------------------------------------------------- coding
-def apply(mat: np.ndarray, blocks) -> list:
+def _run_ranges(rows, cols, mat, ins, outs, S, threads):
+    """oracle_apply_range over [0, S/8) cut into ``threads`` contiguous,
+    disjoint offset ranges, each on its own host thread (the C call releases
+    the interpreter lock; every range writes only its own bytes)."""
+    L = S // 8
+    mat = np.ascontiguousarray(mat, dtype=np.uint8)
+    pin, pout = _ptrs(ins), _ptrs(outs)
+    T = max(1, min(int(threads), L))
+    cuts = [L * t // T for t in range(T + 1)]
+
+    def one(t):
+        return lib().oracle_apply_range(rows, cols, _u8(mat), pin, pout, S, cuts[t], cuts[t + 1])
+
+    if T == 1:
+        rcs = [one(0)]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=T) as ex:
+            rcs = list(ex.map(one, range(T)))
+    bad = [rc for rc in rcs if rc != 0]
+    if bad:
+        raise ValueError("oracle_apply_range rc=%d" % bad[0])
+
+
+def apply(mat: np.ndarray, blocks, threads: int = 1) -> list:
     mat = np.ascontiguousarray(mat, dtype=np.uint8)
     rows, cols = mat.shape
     assert len(blocks) == cols
     S = blocks[0].size
     outs = [np.zeros(S, dtype=np.uint8) for _ in range(rows)]
-    rc = lib().oracle_apply(rows, cols, _u8(mat), _ptrs(blocks), _ptrs(outs), S)
-    if rc != 0:
-        raise ValueError("oracle_apply rc=%d" % rc)
+    _run_ranges(rows, cols, mat, blocks, outs, S, threads)
     return outs
 
 
-def encode(gen: np.ndarray, n: int, p: int, data) -> list:
-    """Parity blocks for the n data blocks (each a uint8 array of S bytes)."""
+def encode(gen: np.ndarray, n: int, p: int, data, threads: int = 1) -> list:
+    """Parity blocks for the n data blocks (each a uint8 array of S bytes);
+    ``threads`` > 1 splits the strip offsets over that many host threads."""
     gen = np.ascontiguousarray(gen, dtype=np.uint8)
     assert len(data) == n
     S = data[0].size
     par = [np.zeros(S, dtype=np.uint8) for _ in range(p)]
+    if threads > 1:
+        if p:
+            _run_ranges(p, n, gen[n:], data, par, S, threads)
+        return par
     rc = lib().oracle_encode(n, p, _u8(gen), _ptrs(data), _ptrs(par), S)
     if rc != 0:
         raise ValueError("oracle_encode rc=%d" % rc)
     return par
 
 
-def decode(gen: np.ndarray, n: int, p: int, erased, blocks) -> list:
+def decode(gen: np.ndarray, n: int, p: int, erased, blocks, threads: int = 1) -> list:
     """Reconstruct every erased block.  ``blocks`` has n+p entries; erased
-    entries are ignored (may be None)."""
+    entries are ignored (may be None).  ``threads`` as in ``encode``."""
     gen = np.ascontiguousarray(gen, dtype=np.uint8)
     S = next(b.size for i, b in enumerate(blocks) if i not in set(erased) and b is not None)
+    if threads > 1:
+        D, R = decode_matrix(gen, n, p, erased)
+        outs = [np.zeros(S, dtype=np.uint8) for _ in erased]
+        if len(erased):
+            _run_ranges(len(erased), n, D, [blocks[r] for r in R], outs, S, threads)
+        return outs
     er = (ctypes.c_int * max(1, len(erased)))(*[int(e) for e in erased])
     outs = [np.zeros(S, dtype=np.uint8) for _ in erased]
     rc = lib().oracle_decode(n, p, _u8(gen), er, len(erased), _ptrs(blocks), _ptrs(outs), S)

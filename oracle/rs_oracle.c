@@ -158,16 +158,21 @@ void oracle_bitmatrix(int rows, int cols, const uint8_t *mat, uint8_t *bits) {
 }
 
 /* Core of both encode and decode: out_j = sum_i mat[j][i] * in_i, symbol by
- * symbol, for every byte offset k of the strips and every bit position b.
- * in: cols pointers to S-byte blocks; out: rows pointers to S-byte blocks. */
-int oracle_apply(int rows, int cols, const uint8_t *mat, const uint8_t *const *in,
-                 uint8_t *const *out, size_t S) {
+ * symbol, for the byte offsets k0 <= k < k1 of the strips and every bit
+ * position b.  in: cols pointers to S-byte blocks; out: rows pointers to
+ * S-byte blocks, of which only offsets [k0, k1) of each strip are written.
+ * Byte offsets are independent of each other (the symbols at offset k are
+ * made of the strips' bytes at k alone), so disjoint ranges may run on
+ * separate threads. */
+int oracle_apply_range(int rows, int cols, const uint8_t *mat, const uint8_t *const *in,
+                       uint8_t *const *out, size_t S, size_t k0, size_t k1) {
   if (S % 8) return -1;
   const size_t L = S / 8;
+  if (k0 > k1 || k1 > L) return -1;
   uint8_t *x = (uint8_t *)malloc((size_t)cols);
   uint8_t *acc = (uint8_t *)malloc((size_t)rows * 8);
   if (!x || !acc) { free(x); free(acc); return -2; }
-  for (size_t k = 0; k < L; ++k) {
+  for (size_t k = k0; k < k1; ++k) {
     memset(acc, 0, (size_t)rows * 8);
     for (int b = 0; b < 8; ++b) {
       /* gather: symbol of block i at (k, b) */
@@ -189,6 +194,13 @@ int oracle_apply(int rows, int cols, const uint8_t *mat, const uint8_t *const *i
   free(x);
   free(acc);
   return 0;
+}
+
+/* The whole strips: offsets [0, S/8). */
+int oracle_apply(int rows, int cols, const uint8_t *mat, const uint8_t *const *in,
+                 uint8_t *const *out, size_t S) {
+  if (S % 8) return -1;
+  return oracle_apply_range(rows, cols, mat, in, out, S, 0, S / 8);
 }
 
 /* Encode: parity_j = sum_i P[j][i] * data_i, with P the last p rows of gen. */

@@ -41,11 +41,13 @@ class StripeSpec:
 
 class ProgramCache:
     """Compiled programs keyed by (n, p, erased, level, slots); thread-safe.
-    The generator is the Cauchy matrix of each codec."""
+    The generator of each codec is ``generator_fn(n, p)`` ((n+p) x n rows),
+    by default the library's Cauchy matrix."""
 
-    def __init__(self, level: int = LEVEL_PLAIN, slots: int = 40):
+    def __init__(self, level: int = LEVEL_PLAIN, slots: int = 40, generator_fn=None):
         self.level = level
         self.slots = slots
+        self._gen_fn = generator_fn or ec_matrix_cauchy
         self._progs = {}
         self._gens = {}
         self._lock = threading.Lock()
@@ -54,7 +56,7 @@ class ProgramCache:
         with self._lock:
             g = self._gens.get((n, p))
             if g is None:
-                g = self._gens[(n, p)] = ec_matrix_cauchy(n, p)
+                g = self._gens[(n, p)] = [[int(x) for x in row] for row in self._gen_fn(n, p)]
             return g
 
     def get(self, n, p, erased=()):
@@ -109,6 +111,31 @@ def mixed_specs(count: int, seed: int, codecs=CODECS_DEFAULT, lo=4096, hi=4 << 2
             erased = pats[key][int(rng.integers(len(pats[key])))]
         out.append(StripeSpec(n, p, int(sizes[k]), erased))
     return out
+
+
+def mixed_workload(count: int, seed: int = 4, hi: int = 4 << 20, pool_bytes: int = 4 << 30, slice_seed: int = 5):
+    """The batched benchmark's stripes and buffers: ``mixed_specs(count,
+    seed, hi=hi)``; every input block a 4 KiB-aligned slice, at an offset
+    drawn from ``slice_seed``, of one pool of ``pool_bytes`` seeded random
+    bytes on the device (read-only, so stripes may share bytes); every
+    output block its own range of one output buffer.  Returns (specs, pool,
+    inputs, outputs, out_buf) with inputs[k] / outputs[k] lists of tensor
+    views in program argument order."""
+    import torch
+    specs = mixed_specs(count, seed=seed, hi=hi)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    rng = np.random.default_rng(slice_seed)
+    out_total = sum(s.n_out * s.block_bytes for s in specs)
+    out_buf = torch.empty(out_total, dtype=torch.uint8, device="cuda")
+    inputs, outputs, off = [], [], 0
+    for s in specs:
+        top = (pool_bytes - s.block_bytes) // 4096
+        inputs.append([pool[o:o + s.block_bytes] for o in (rng.integers(0, top, s.n_in) * 4096).tolist()])
+        outputs.append([out_buf[off + j * s.block_bytes: off + (j + 1) * s.block_bytes] for j in range(s.n_out)])
+        off += s.n_out * s.block_bytes
+    return specs, pool, inputs, outputs, out_buf
 
 
 def build_batch(specs, cache: ProgramCache, inputs, outputs, tile_bytes=0, stream=None):

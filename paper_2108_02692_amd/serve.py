@@ -92,7 +92,8 @@ class Server:
     loop in Python (the methods below), kept for comparison."""
 
     def __init__(self, budget_bytes=16 << 30, n_slots=4, max_batch=512, level=LEVEL_CO_FU_SCHED, slots=38,
-                 tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True, direct_single=True, native=True):
+                 tile_bytes=0, codecs=((10, 4), (6, 3)), warm=True, direct_single=True, native=True,
+                 generator_fn=None):
         import torch
         self.torch = torch
         self.budget = budget_bytes
@@ -100,7 +101,7 @@ class Server:
         self.max_batch = max_batch
         self.tile_bytes = tile_bytes
         self.direct_single = direct_single
-        self.cache = ProgramCache(level=level, slots=slots)
+        self.cache = ProgramCache(level=level, slots=slots, generator_fn=generator_fn)
         if warm:
             self.cache.warm([(n, p, er) for n, p in codecs for er in self.cache.all_patterns(n, p)])
             # every program resident on the device before the clock starts

@@ -63,10 +63,14 @@ def eval_export(stmts, outs):
 CODECS = [(10, 4), (6, 3), (12, 4), (14, 4)]
 
 
-@pytest.mark.parametrize("n,p", CODECS)
-def test_generator_matches_oracle(n, p):
-    assert np.array_equal(np.array(E.ec_matrix_cauchy(n, p), dtype=np.uint8), oracle.cauchy(n, p))
-    assert np.array_equal(np.array(E.ec_matrix_vandermonde(n, p), dtype=np.uint8), oracle.vandermonde_rows(n, p))
+def test_generator_matches_oracle():
+    """Every codec the library's generators accept (n >= 1, p >= 0,
+    n + p <= 64)."""
+    for n in range(1, 65):
+        for p in range(0, 65 - n):
+            assert np.array_equal(np.array(E.ec_matrix_cauchy(n, p), dtype=np.uint8), oracle.cauchy(n, p)), (n, p)
+            assert np.array_equal(np.array(E.ec_matrix_vandermonde(n, p), dtype=np.uint8),
+                                  oracle.vandermonde_rows(n, p)), (n, p)
 
 
 def sample_patterns(n, p, k, seed):

@@ -14,6 +14,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def oracle_gen(n, p):
+    """The oracle's Cauchy generator, as the rows the library takes."""
+    return [[int(x) for x in row] for row in oracle.cauchy(n, p)]
+
+
 def make_case(specs, cache, seed):
     """Host inputs and expected outputs per stripe (expected from the oracle)."""
     rng = np.random.default_rng(seed)
@@ -43,7 +48,7 @@ def check(outs, want, what):
                                               (E.LEVEL_CO_FU_SCHED, 44, 0), (E.LEVEL_CO_FU_SCHED, 24, 2048)])
 def test_batch_mixed_matches_oracle_and_graph_replays(level, slots, tile):
     specs = B.mixed_specs(96, seed=5, lo=4096, hi=64 * 1024)
-    cache = B.ProgramCache(level=level, slots=slots)
+    cache = B.ProgramCache(level=level, slots=slots, generator_fn=oracle.cauchy)
     ins_h, want = make_case(specs, cache, seed=6)
     ins = [W.to_device(x) for x in ins_h]
     outs = [W.empty_blocks(s.n_out, s.block_bytes, fill=0xA5) for s in specs]
@@ -65,7 +70,7 @@ def test_batch_mixed_matches_oracle_and_graph_replays(level, slots, tile):
 
 
 def test_batch_rejects_mixed_slot_budgets():
-    gen = E.ec_matrix_cauchy(6, 3)
+    gen = oracle_gen(6, 3)
     a = E.ec_compile_slp(6, 3, gen, level=E.LEVEL_PLAIN, slot_budget=40)
     b = E.ec_compile_slp(6, 3, gen, level=E.LEVEL_PLAIN, slot_budget=48)
     d = W.empty_blocks(6, 4096, fill=0)
@@ -79,7 +84,7 @@ def test_reusable_batch_reserve_and_refill():
     """create + reserve + set/enqueue twice with different stripes (the
     serving pattern), programs uploaded beforehand; both runs match the
     oracle."""
-    cache = B.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=38)
+    cache = B.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=38, generator_fn=oracle.cauchy)
     stream = torch.cuda.current_stream()
     batch = E.Batch.create()
     batch.reserve(64, 4096)
@@ -110,7 +115,7 @@ def test_batch_edge_shapes_and_mixed_levels(split):
              (6, 3, (), 3 * 8192 + 128), (14, 4, (0, 13), 4096 + 128), (10, 4, (), 128), (12, 4, (15,), 8 * 1024 * 9)]
     stripes, want, keep = [], [], []
     for k, (n, p, er, S) in enumerate(cases):
-        gen = E.ec_matrix_cauchy(n, p)
+        gen = oracle_gen(n, p)
         G = np.array(gen, dtype=np.uint8)
         level = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU_SCHED)[k % 3]
         prog = E.ec_compile_slp(n, p, gen, list(er), level=level, slot_budget=44,
@@ -145,7 +150,7 @@ def test_batch_edge_shapes_and_mixed_levels(split):
 
 
 def test_batch_argument_errors():
-    gen = E.ec_matrix_cauchy(6, 3)
+    gen = oracle_gen(6, 3)
     prog = E.ec_compile_slp(6, 3, gen, slot_budget=38)
     d = W.empty_blocks(6, 4096, fill=0)
     o = W.empty_blocks(3, 4096)

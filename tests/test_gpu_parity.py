@@ -4,6 +4,7 @@ Every comparison is byte-exact (the path is integer XOR only).  Inputs come
 from the seeded generators in ``paper_2108_02692_amd.workloads``; expected
 values come from the oracle only: parity blocks from ``oracle.encode`` and,
 for decode, the original blocks themselves (the oracle's encode of the data).
+Every program is compiled from the oracle's generator matrix.
 """
 import functools
 import itertools
@@ -21,6 +22,11 @@ from paper_2108_02692_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+
+def oracle_gen(n, p):
+    """The oracle's Cauchy generator, as the rows the library takes."""
+    return [[int(x) for x in row] for row in oracle.cauchy(n, p)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -55,7 +61,7 @@ def assert_blocks_equal(got, want, what):
 @functools.lru_cache(maxsize=None)
 def rs10_4_1mib():
     n, p, S = 10, 4, 1 << 20
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=0)
     return gen, data, oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
 
@@ -81,7 +87,7 @@ def test_encode_rs10_4_1mib(level, K):
 def test_encode_ragged_sizes(S):
     """Block sizes that leave a partial tile (1 KiB per strip per wave)."""
     n, p = 10, 4
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=S)
     want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
     for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
@@ -95,7 +101,7 @@ CODECS = [(6, 3), (12, 4), (14, 4), (8, 4), (9, 4), (8, 3), (9, 3), (10, 3), (8,
 @pytest.mark.parametrize("n,p", CODECS)
 def test_encode_other_codecs(n, p):
     S = 64 * 1024
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=n * 10 + p)
     want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
     for K in (0, 24, 48):
@@ -107,7 +113,7 @@ def test_encode_row_passes_and_block_widths():
     """RS(8,8) needs several passes over the inputs (64 rows > slots);
     RS(10,4) with other column-block widths."""
     S = 64 * 1024 + 128
-    gen = E.ec_matrix_cauchy(8, 8)
+    gen = oracle_gen(8, 8)
     data = W.host_blocks(8, S, seed=88)
     want = oracle.encode(np.array(gen, dtype=np.uint8), 8, 8, data)
     for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
@@ -123,7 +129,7 @@ def test_encode_row_passes_and_block_widths():
 @pytest.mark.parametrize("dist", [4, 12, 20])
 def test_encode_decode_with_prefetch(dist):
     n, p, S = 10, 4, (1 << 20) + 640
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=dist)
     blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
     for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
@@ -140,7 +146,7 @@ def test_degenerate_and_wide_codecs(n, p, er):
     """Replication (n = 1), the widest stripe (32 blocks), more rows than
     slots (RS(4,12): several passes over the inputs) and no parity at all."""
     S = 8192 + 128
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=n * 100 + p)
     blocks = data + (oracle.encode(np.array(gen, dtype=np.uint8), n, p, data) if p else [])
     for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
@@ -161,7 +167,7 @@ def test_decode_rs10_4_every_pattern():
     Recovered blocks must equal the originals (data from the generator,
     parity from the oracle)."""
     n, p, S = 10, 4, 2048
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=7)
     blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
     dev = W.to_device(blocks)
@@ -178,7 +184,7 @@ def test_decode_rs10_4_every_pattern():
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
 def test_decode_rs10_4_1mib(er, level):
     n, p, S = 10, 4, 1 << 20
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=1)
     blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
     prog = E.ec_compile_slp(n, p, gen, er, level=level)
@@ -188,7 +194,7 @@ def test_decode_rs10_4_1mib(er, level):
 @pytest.mark.parametrize("n,p", CODECS)
 def test_decode_other_codecs_sampled(n, p):
     S = 4096
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=3 * n + p)
     blocks = data + oracle.encode(np.array(gen, dtype=np.uint8), n, p, data)
     rng = random.Random(n)
@@ -197,58 +203,13 @@ def test_decode_other_codecs_sampled(n, p):
         assert_blocks_equal(run_decode(prog, blocks, S), [blocks[e] for e in er], "RS(%d,%d) %s" % (n, p, er))
 
 
-def test_encode_64mib_sampled():
-    """The benchmark's configuration (10 x 64 MiB, default program): outputs
-    checked on sampled strip offsets, each sample coded by the oracle."""
-    n, p, S = 10, 4, 64 << 20
-    gen = E.ec_matrix_cauchy(n, p)
-    data = W.device_blocks(n, S, seed=11)
-    par = W.empty_blocks(p, S, fill=0xA5)
-    for level in (E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN):
-        prog = E.ec_compile_slp(n, p, gen, level=level)
-        E.ec_encode(prog, data, par, S)
-        torch.cuda.synchronize()
-        L = S // 8
-        offs = [0, 1024, L // 2 + 48, L - 1024, L - 16]
-        mini = [W.strip_sample(b, offs, 16).cpu().numpy() for b in data]
-        want = oracle.encode(np.array(gen, dtype=np.uint8), n, p, mini)
-        got = [W.strip_sample(b, offs, 16).cpu().numpy() for b in par]
-        assert_blocks_equal(got, want, "64 MiB level %d" % level)
-
-
-@pytest.mark.parametrize("er", [(4, 5, 6, 7), (2, 4, 5, 6), (0, 11, 13)])
-def test_decode_64mib_sampled(er):
-    """Decode at the benchmark's block size (10 x 64 MiB, default program),
-    in the launch the benchmark times: every erased block checked on sampled
-    strip offsets against the oracle's decode of the same samples."""
-    n, p, S = 10, 4, 64 << 20
-    gen = E.ec_matrix_cauchy(n, p)
-    G = np.array(gen, dtype=np.uint8)
-    data = W.device_blocks(n, S, seed=12)
-    par = W.empty_blocks(p, S)
-    E.ec_encode(E.ec_compile_slp(n, p, gen), data, par, S)
-    blocks = data + par
-    prog = E.ec_compile_slp(n, p, gen, list(er))
-    rec = W.empty_blocks(len(er), S, fill=0xA5)
-    E.ec_decode(prog, [blocks[i] for i in prog.in_blocks], rec, S)
-    torch.cuda.synchronize()
-    L = S // 8
-    offs = [0, 2048, L // 3 + 16, L - 1024, L - 16]
-    mini = [W.strip_sample(b, offs, 16).cpu().numpy() for b in blocks[:n]]
-    mini = mini + oracle.encode(G, n, p, mini)
-    want = oracle.decode(G, n, p, list(er), [None if i in er else mini[i] for i in range(n + p)])
-    got = [W.strip_sample(r, offs, 16).cpu().numpy() for r in rec]
-    assert_blocks_equal(got, [want[list(er).index(e)] for e in prog.out_blocks], "64 MiB decode %s" % (er,))
-    assert_blocks_equal(got, [mini[e] for e in prog.out_blocks], "64 MiB decode %s vs data" % (er,))
-
-
 def test_largest_block_sampled():
     """The largest block the executor takes (4 GiB - 128 B: strips of just
     under 512 MiB, strip offsets past 2^31 within a block), RS(4,2) encode
     and a two-block decode, checked on sampled strip offsets against the
     oracle."""
     n, p, S = 4, 2, (1 << 32) - 128
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     G = np.array(gen, dtype=np.uint8)
     data = W.device_blocks(n, S, seed=13)
     par = W.empty_blocks(p, S, fill=0xA5)
@@ -272,7 +233,7 @@ def test_largest_block_sampled():
 
 def test_outputs_fully_written_and_inputs_untouched():
     n, p, S = 10, 4, 4096 + 128
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     data = W.host_blocks(n, S, seed=5)
     d = W.to_device(data)
     prog = E.ec_compile_slp(n, p, gen)
@@ -287,7 +248,7 @@ def test_outputs_fully_written_and_inputs_untouched():
 
 def test_two_streams_concurrently():
     n, p, S = 10, 4, 1 << 18
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     prog_a = E.ec_compile_slp(n, p, gen)
     prog_b = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=48)
     da, db = W.host_blocks(n, S, seed=21), W.host_blocks(n, S, seed=22)
@@ -311,7 +272,7 @@ def test_graph_captured_launches_replay(S):
     oracle on that replay's inputs (256 KiB blocks take row parts, 4 MiB
     block parts)."""
     n, p, er = 10, 4, [2, 4, 5, 11]
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     G = np.array(gen, dtype=np.uint8)
     enc = E.ec_compile_slp(n, p, gen)
     dec = E.ec_compile_slp(n, p, gen, er)
@@ -345,7 +306,7 @@ def test_graph_captured_launches_replay(S):
 
 def test_launch_argument_errors():
     n, p, S = 10, 4, 4096
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     prog = E.ec_compile_slp(n, p, gen)
     dec = E.ec_compile_slp(n, p, gen, [1])
     d = W.empty_blocks(n, S, fill=0)
@@ -374,7 +335,7 @@ def test_row_split_matches_oracle(n, p, er):
     """Short stripes run one wave per (tile, part): row, pair and block parts
     forced, the split off and left to the library, on ragged and small block
     sizes, equal the oracle."""
-    gen = E.ec_matrix_cauchy(n, p)
+    gen = oracle_gen(n, p)
     G = np.array(gen, dtype=np.uint8)
     for S in (4096 + 128, 1 << 20, 3 * (1 << 20) + 384):
         data = W.host_blocks(n, S, seed=S % 1000 + n)
@@ -401,7 +362,7 @@ def test_random_cases_match_oracle():
         k = rng.randint(0, p)
         er = tuple(sorted(rng.sample(range(n + p), k)))
         S = 128 * rng.randint(1, 3072)
-        gen = E.ec_matrix_cauchy(n, p)
+        gen = oracle_gen(n, p)
         try:
             prog = E.ec_compile_slp(n, p, gen, list(er), level=rng.choice(levels),
                                     slot_budget=rng.choice(budgets), split=rng.choice(splits))

@@ -39,7 +39,8 @@ def test_mix_equals_alone_equals_oracle(native):
     assert len(reqs) > 40
     # A budget far below the total forces admission back-pressure and many
     # batches in flight; small batches interleave codecs and sizes.
-    server = SV.Server(budget_bytes=16 << 20, n_slots=3, max_batch=7, warm=False, native=native)
+    server = SV.Server(generator_fn=oracle.cauchy, budget_bytes=16 << 20, n_slots=3, max_batch=7, warm=False,
+                       native=native)
     for r in reqs:
         server.cache.get(r.n, r.p, r.erased)
     for r in reqs:
@@ -79,7 +80,7 @@ def test_native_loop_realtime_and_argument_errors():
     pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
     pool_h = pool.cpu().numpy()
     reqs = SV.make_requests(0.01, 20000.0, seed=6, pool_ptr=pool.data_ptr(), pool_bytes=pool_bytes, hi=1 << 20)
-    server = SV.Server(budget_bytes=64 << 20, n_slots=4, max_batch=16, warm=False)
+    server = SV.Server(generator_fn=oracle.cauchy, budget_bytes=64 << 20, n_slots=4, max_batch=16, warm=False)
     got = {}
 
     def grab(done):
@@ -98,7 +99,7 @@ def test_native_loop_realtime_and_argument_errors():
     with pytest.raises(EcError) as e:
         server.serve([a, b])  # arrivals out of order
     assert e.value.name == "EC_ERR_ARG"
-    small = SV.Server(budget_bytes=256 << 10, n_slots=2, max_batch=4, warm=False)
+    small = SV.Server(generator_fn=oracle.cauchy, budget_bytes=256 << 10, n_slots=2, max_batch=4, warm=False)
     big = max(reqs, key=lambda r: r.bytes)
     big.arrival = 0.0
     assert big.bytes > 256 << 10
@@ -119,7 +120,7 @@ def test_native_loop_mixed_slot_budgets():
     pool = torch.from_numpy(pool_h).cuda()
     arena = torch.empty(32 << 20, dtype=torch.uint8, device="cuda")
     codecs = [(10, 4, (), 38), (4, 2, (), 24), (6, 3, (1, 7), 32), (10, 4, (2, 4, 5, 11), 38)]
-    progs = {c: E.ec_compile_slp(c[0], c[1], E.ec_matrix_cauchy(c[0], c[1]), list(c[2]), slot_budget=c[3])
+    progs = {c: E.ec_compile_slp(c[0], c[1], oracle.cauchy(c[0], c[1]).tolist(), list(c[2]), slot_budget=c[3])
              for c in codecs}
     reqs, meta = [], []
     for k in range(40):
@@ -141,7 +142,7 @@ def test_native_loop_mixed_slot_budgets():
     assert len(got) == len(reqs) and all(t >= 0 for t in done) and nb >= 10
     for i, (c, ins, bb) in enumerate(meta):
         n, p, er, _ = c
-        G = np.array(E.ec_matrix_cauchy(n, p), dtype=np.uint8)
+        G = oracle.cauchy(n, p)
         data = [pool_h[o: o + bb] for o in ins]
         if er:
             D, surv = oracle.decode_matrix(G, n, p, list(er))
