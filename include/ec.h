@@ -58,7 +58,8 @@ typedef enum {
   EC_ERR_DEVICE = 6,            /* HIP runtime error (no device, launch failure) */
   EC_ERR_UNSUPPORTED = 7,       /* option or size outside what the executor supports */
   EC_ERR_CAPACITY = 8           /* program does not fit the register slot budget; or a
-                                   request does not fit a server's budget or arena */
+                                   request does not fit a server's budget or arena; or a
+                                   batch does not fit ec_batch_run_noalloc's fixed tables */
 } ec_status;
 
 /* Optimisation level of a compiled program (the stages of Sec. 7.5). */
@@ -297,6 +298,36 @@ ec_status ec_batch_reserve(ec_batch *batch, int n_stripes, size_t n_items);
 ec_status ec_batch_query(const ec_batch *batch, size_t *n_items, size_t *in_bytes, size_t *out_bytes);
 
 void ec_batch_free(ec_batch *batch);
+
+/* ---- for callers that cannot allocate
+ *
+ * For code that must not allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one batched
+ * launch over `stripes`, as ec_batch_set + ec_batch_enqueue on `stream`,
+ * whose work counter, stripe descriptors and work items live in a fixed
+ * device array of EC_NOALLOC_SCRATCH_BYTES per device (part of the library,
+ * held by each device it runs on until the process ends) instead of memory
+ * the library allocates.  The call allocates nothing, on the device or the
+ * host: it fills the tables in a static host array, copies them into the
+ * device array with hipMemcpyAsync on `stream` and launches.
+ *  - Every call on one device shares that device's array: calls on the same
+ *    stream run in order, but calls whose launches overlap on one device
+ *    (different streams, or threads racing to different streams) race on
+ *    the array and give undefined results.  Host threads are serialised
+ *    inside the call.
+ *  - Every program must already be on the current device (ec_program_upload
+ *    or an earlier launch with it): a program that is not gives EC_ERR_ARG,
+ *    since uploading it would allocate.
+ *  - At most EC_NOALLOC_MAX_STRIPES stripes, and work items (one per
+ *    tile_bytes of a strip, times the parts of the batch's row split) within
+ *    what the array holds after the descriptors (997,312):
+ *    EC_ERR_CAPACITY otherwise.
+ *  - Otherwise the same arguments, rules and errors as ec_batch_set
+ *    (outputs disjoint from each other and from every input).  Results are
+ *    those of ec_batch_build / ec_batch_launch on the same stripes. */
+#define EC_NOALLOC_SCRATCH_BYTES (8u << 20)
+#define EC_NOALLOC_MAX_STRIPES 1024
+ec_status ec_batch_run_noalloc(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream);
 
 /* ---- serving: a request loop with continuous batching
  *

@@ -17,7 +17,8 @@ from . import _build
 
 __all__ = [
     "EcError", "Program", "ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp",
-    "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_device_copy", "lib",
+    "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_batch_run_noalloc", "ec_device_copy",
+    "lib",
     "Server", "ec_server_create",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
@@ -121,6 +122,7 @@ def lib():
         L.ec_batch_set.argtypes = [vp, ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp]
         L.ec_batch_query.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                      ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_batch_run_noalloc.argtypes = [ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp]
         L.ec_batch_free.argtypes = [vp]
         L.ec_batch_free.restype = None
         L.ec_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
@@ -132,6 +134,7 @@ def lib():
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
                      "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_program_part_bytecode", "ec_batch_build", "ec_device_copy",
                      "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set",
+                     "ec_batch_run_noalloc",
                      "ec_server_create", "ec_server_run"):
             getattr(L, name).restype = st
         _lib = L
@@ -388,6 +391,15 @@ def ec_batch_build(stripes, tile_bytes: int = 0, stream=None) -> Batch:
     _check(lib().ec_batch_build(arr, n, tile_bytes, _stream_handle(stream), ctypes.byref(h)),
            "ec_batch_build")
     return Batch(h.value, keep)
+
+
+def ec_batch_run_noalloc(stripes, tile_bytes: int = 0, stream=None):
+    """One batched launch over ``stripes`` ((Program, inputs, outputs,
+    block_bytes)) whose tables live in the library's fixed per-device array:
+    no allocation (every program must be uploaded to the device first).
+    Launches overlapping on one device race on that array."""
+    arr, keep, n = _stripe_array(stripes)
+    _check(lib().ec_batch_run_noalloc(arr, n, tile_bytes, _stream_handle(stream)), "ec_batch_run_noalloc")
 
 
 class Server:

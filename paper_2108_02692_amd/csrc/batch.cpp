@@ -9,12 +9,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <memory>
 #include <new>
 #include <utility>
 #include <vector>
 
 #include "../../include/ec.h"
+#include "batch.hpp"
 #include "exec.hpp"
 #include "program.hpp"
 
@@ -54,32 +56,154 @@ namespace {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+bool by_first(const ByteRange &a, const ByteRange &b) {
+  return a.first < b.first || (a.first == b.first && a.second < b.second);
+}
+
 // The stripes of one launch run in no defined order, so every byte written
 // must be written by one output block only and read by none: the written
 // ranges are pairwise disjoint and disjoint from every read range (reads
-// may overlap each other).  Ranges are [begin, end).
-bool disjoint_writes(std::vector<std::pair<uintptr_t, uintptr_t>> &reads,
-                     std::vector<std::pair<uintptr_t, uintptr_t>> &writes) {
-  std::sort(writes.begin(), writes.end());
-  for (size_t k = 1; k < writes.size(); ++k)
+// may overlap each other).  Sorts both arrays and merges the reads in place.
+bool disjoint_writes(ByteRange *reads, size_t n_reads, ByteRange *writes, size_t n_writes) {
+  std::sort(writes, writes + n_writes, by_first);
+  for (size_t k = 1; k < n_writes; ++k)
     if (writes[k].first < writes[k - 1].second) return false;
-  // merge the read ranges, then look up each write among them
-  std::sort(reads.begin(), reads.end());
-  std::vector<std::pair<uintptr_t, uintptr_t>> merged;
-  for (const auto &r : reads) {
-    if (!merged.empty() && r.first <= merged.back().second)
-      merged.back().second = std::max(merged.back().second, r.second);
+  std::sort(reads, reads + n_reads, by_first);
+  size_t m = 0;  // merged read ranges, in reads[0, m)
+  for (size_t k = 0; k < n_reads; ++k) {
+    if (m && reads[k].first <= reads[m - 1].second)
+      reads[m - 1].second = std::max(reads[m - 1].second, reads[k].second);
     else
-      merged.push_back(r);
+      reads[m++] = reads[k];
   }
-  for (const auto &w : writes) {
+  for (size_t k = 0; k < n_writes; ++k) {
+    const ByteRange &w = writes[k];
     // first merged read range ending after the write begins
-    auto it = std::upper_bound(merged.begin(), merged.end(), w.first,
-                               [](uintptr_t x, const std::pair<uintptr_t, uintptr_t> &r) { return x < r.second; });
-    if (it != merged.end() && it->first < w.second) return false;
+    const ByteRange *it = std::upper_bound(reads, reads + m, w.first,
+                                           [](uintptr_t x, const ByteRange &r) { return x < r.second; });
+    if (it != reads + m && it->first < w.second) return false;
   }
   return true;
 }
+
+// The part offsets a stripe's work items name under the batch's split.
+const std::vector<uint32_t> *split_offsets(const ec_program *prog, const BatchPlan &plan) {
+  if (prog->split == EC_SPLIT_ROWS || (prog->split == EC_SPLIT_AUTO && plan.rows_fit))
+    return prog->row_parts.empty() ? nullptr : &prog->row_part_off;
+  if (prog->split == EC_SPLIT_PAIRS || (prog->split == EC_SPLIT_AUTO && plan.pairs_fit))
+    return prog->pair_parts.empty() ? nullptr : &prog->pair_part_off;
+  if (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && plan.blocks_fit))
+    return prog->parts.empty() ? nullptr : &prog->part_off;
+  return nullptr;
+}
+
+uint32_t n_tiles_of(size_t block_bytes) { return (uint32_t)((block_bytes / 8 + kTileBytes - 1) / kTileBytes); }
+
+}  // namespace
+
+namespace ec {
+
+ec_status batch_plan(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, int n_cus, BatchPlan *plan) {
+  if (!stripes || n_stripes <= 0 || !plan) return EC_ERR_ARG;
+  if (tile_bytes == 0) tile_bytes = kTileBytes;
+  if (tile_bytes % kTileBytes != 0 || tile_bytes / kTileBytes > 4096) return EC_ERR_UNSUPPORTED;
+  BatchPlan pl;
+  pl.tiles_per_item = (uint32_t)(tile_bytes / kTileBytes);
+  uint64_t items_rows = 0, items_pairs = 0, items_blocks = 0;  // work items with each set of parts
+  for (int s = 0; s < n_stripes; ++s) {
+    const ec_stripe &st = stripes[s];
+    const ec_program *prog = st.prog;
+    if (!prog || !st.in || !st.out) return EC_ERR_ARG;
+    if (st.block_bytes == 0 || st.block_bytes % 128 != 0) return EC_ERR_ALIGN;
+    if (st.block_bytes / 8 > 0x1FFFFFFFull) return EC_ERR_UNSUPPORTED;
+    if (s == 0) pl.slots = prog->slots;
+    else if (prog->slots != pl.slots) return EC_ERR_UNSUPPORTED;  // one kernel instance per launch
+    const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+    for (int i = 0; i < n_in; ++i)
+      if (!st.in[i]) return EC_ERR_ARG;
+      else if (!aligned16(st.in[i])) return EC_ERR_ALIGN;
+    for (int j = 0; j < n_out; ++j)
+      if (!st.out[j]) return EC_ERR_ARG;
+      else if (!aligned16(st.out[j])) return EC_ERR_ALIGN;
+    const uint64_t n_tiles = n_tiles_of(st.block_bytes);
+    items_rows += n_tiles * std::max<size_t>(1, prog->row_parts.size());
+    items_pairs += n_tiles * std::max<size_t>(1, prog->pair_parts.size());
+    items_blocks += n_tiles * std::max<size_t>(1, prog->parts.size());
+    pl.in_bytes += (size_t)n_in * st.block_bytes;
+    pl.out_bytes += (size_t)n_out * st.block_bytes;
+    pl.n_ranges_in += (size_t)n_in;
+    pl.n_ranges_out += (size_t)n_out;
+  }
+  // Row split as for one stripe, decided for the whole batch: row parts
+  // when one wave per (tile, row part) of every stripe leaves at most two
+  // waves per SIMD, else pair parts when theirs do, else block parts when
+  // all theirs are resident, else none (stripes compiled with another
+  // policy than EC_SPLIT_AUTO take their own choice).
+  const uint64_t resident_waves = 4ull * (uint64_t)n_cus * waves_per_simd(pl.slots);
+  const uint64_t fine_waves = 2ull * 4 * (uint64_t)n_cus;  // two waves per SIMD
+  pl.rows_fit = items_rows <= fine_waves;
+  pl.pairs_fit = !pl.rows_fit && items_pairs <= fine_waves;
+  pl.blocks_fit = !pl.rows_fit && !pl.pairs_fit && items_blocks <= resident_waves;
+  for (int s = 0; s < n_stripes; ++s) {
+    const std::vector<uint32_t> *off = split_offsets(stripes[s].prog, pl);
+    const uint64_t n_its = (n_tiles_of(stripes[s].block_bytes) + pl.tiles_per_item - 1) / pl.tiles_per_item;
+    pl.n_items += n_its * (off ? off->size() : 1);
+  }
+  if (pl.n_items > 0xFFFFFFFFull) return EC_ERR_UNSUPPORTED;
+  *plan = pl;
+  return EC_OK;
+}
+
+ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &plan, bool upload, StripeDesc *desc,
+                     uint32_t *items, ByteRange *reads, ByteRange *writes) {
+  size_t nr = 0, nw = 0, w = 0;
+  for (int s = 0; s < n_stripes; ++s) {
+    const ec_stripe &st = stripes[s];
+    const ec_program *prog = st.prog;
+    const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+    StripeDesc &d = desc[s];
+    std::memset(&d, 0, sizeof d);  // unused block entries are zero (the kernel reads all 32)
+    for (int i = 0; i < n_in; ++i) {
+      d.blk[i] = (uint64_t)(uintptr_t)st.in[i];
+      reads[nr++] = {(uintptr_t)st.in[i], (uintptr_t)st.in[i] + st.block_bytes};
+    }
+    for (int j = 0; j < n_out; ++j) {
+      d.blk[n_in + j] = (uint64_t)(uintptr_t)st.out[j];
+      writes[nw++] = {(uintptr_t)st.out[j], (uintptr_t)st.out[j] + st.block_bytes};
+    }
+    ec_program *mp = const_cast<ec_program *>(prog);
+    ec_status ws = EC_OK;
+    d.prog = upload ? mp->device_words(&ws) : mp->device_words_present();
+    if (!d.prog) return upload ? ws : EC_ERR_ARG;
+    d.n_blocks = (uint32_t)(n_in + n_out);
+    d.strip_len = (uint32_t)(st.block_bytes / 8);
+    const std::vector<uint32_t> *off = split_offsets(prog, plan);
+    const uint32_t n_parts = off ? (uint32_t)off->size() : 1u;
+    for (uint32_t q = 0; q < (uint32_t)kMaxRowParts; ++q) d.part_off[q] = off && q < n_parts ? (*off)[q] : 0u;
+    const uint32_t n_its = (n_tiles_of(st.block_bytes) + plan.tiles_per_item - 1) / plan.tiles_per_item;
+    // Strips a multiple of 4 MiB apart: consecutive items from 8 distant
+    // segments of the strips (the single-stripe launch does the same).
+    const bool spread = d.strip_len % (4u << 20) == 0 && n_its % 8 == 0;
+    for (uint32_t k = 0; k < n_its; ++k) {
+      const uint32_t i = spread ? (k & 7u) * (n_its >> 3) + (k >> 3) : k;
+      for (uint32_t q = 0; q < n_parts; ++q) {  // a tile's parts side by side
+        items[w++] = (uint32_t)s;
+        items[w++] = i * plan.tiles_per_item | q << kItemPartShift;
+      }
+    }
+  }
+  if (!disjoint_writes(reads, nr, writes, nw)) return EC_ERR_ARG;
+  return EC_OK;
+}
+
+int batch_grid(const BatchPlan &plan, int n_cus) {
+  return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)n_cus * waves_per_simd(plan.slots),
+                                                      (plan.n_items + 3) / 4));
+}
+
+}  // namespace ec
+
+namespace {
 
 // Grows the device tables and their pinned staging to hold n_desc stripes
 // and n_words item words (never shrinks).
@@ -134,89 +258,16 @@ ec_status ec_batch_create(ec_batch **out) {
 
 ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream) {
   if (!b || !stripes || n_stripes <= 0) return EC_ERR_ARG;
-  if (tile_bytes == 0) tile_bytes = kTileBytes;
-  if (tile_bytes % kTileBytes != 0 || tile_bytes / kTileBytes > 4096) return EC_ERR_UNSUPPORTED;
-  const uint32_t tiles_per_item = (uint32_t)(tile_bytes / kTileBytes);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return EC_ERR_DEVICE;
+  BatchPlan plan;
+  ec_status st = batch_plan(stripes, n_stripes, tile_bytes, b->n_cus, &plan);
+  if (st != EC_OK) return st;
   std::vector<StripeDesc> desc((size_t)n_stripes);
-  std::vector<uint32_t> items;
-  // byte ranges read and written by the whole launch
-  std::vector<std::pair<uintptr_t, uintptr_t>> reads, writes;
-  int slots = 0;
-  size_t in_bytes = 0, out_bytes = 0;
-  uint64_t items_rows = 0, items_pairs = 0, items_blocks = 0;  // work items with each set of parts
-  for (int s = 0; s < n_stripes; ++s) {
-    const ec_stripe &st = stripes[s];
-    const ec_program *prog = st.prog;
-    if (!prog || !st.in || !st.out) return EC_ERR_ARG;
-    if (st.block_bytes == 0 || st.block_bytes % 128 != 0) return EC_ERR_ALIGN;
-    if (st.block_bytes / 8 > 0x1FFFFFFFull) return EC_ERR_UNSUPPORTED;
-    if (s == 0) slots = prog->slots;
-    else if (prog->slots != slots) return EC_ERR_UNSUPPORTED;  // one kernel instance per launch
-    const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
-    StripeDesc &d = desc[s];
-    for (int i = 0; i < n_in; ++i) {
-      if (!st.in[i]) return EC_ERR_ARG;
-      if (!aligned16(st.in[i])) return EC_ERR_ALIGN;
-      d.blk[i] = (uint64_t)(uintptr_t)st.in[i];
-      reads.push_back({(uintptr_t)st.in[i], (uintptr_t)st.in[i] + st.block_bytes});
-    }
-    for (int j = 0; j < n_out; ++j) {
-      if (!st.out[j]) return EC_ERR_ARG;
-      if (!aligned16(st.out[j])) return EC_ERR_ALIGN;
-      d.blk[n_in + j] = (uint64_t)(uintptr_t)st.out[j];
-      writes.push_back({(uintptr_t)st.out[j], (uintptr_t)st.out[j] + st.block_bytes});
-    }
-    ec_status ws = EC_OK;
-    d.prog = const_cast<ec_program *>(prog)->device_words(&ws);
-    if (!d.prog) return ws;
-    d.n_blocks = (uint32_t)(n_in + n_out);
-    d.strip_len = (uint32_t)(st.block_bytes / 8);
-    const uint64_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
-    items_rows += n_tiles * std::max<size_t>(1, prog->row_parts.size());
-    items_pairs += n_tiles * std::max<size_t>(1, prog->pair_parts.size());
-    items_blocks += n_tiles * std::max<size_t>(1, prog->parts.size());
-    in_bytes += (size_t)n_in * st.block_bytes;
-    out_bytes += (size_t)n_out * st.block_bytes;
-  }
-  // Row split as for one stripe, decided for the whole batch: row parts
-  // when one wave per (tile, row part) of every stripe leaves at most two
-  // waves per SIMD, else pair parts when theirs do, else block parts when
-  // all theirs are resident, else none (stripes compiled with another
-  // policy than EC_SPLIT_AUTO take their own choice).
-  const uint64_t resident_waves = 4ull * (uint64_t)b->n_cus * waves_per_simd(slots);
-  const uint64_t fine_waves = 2ull * 4 * (uint64_t)b->n_cus;  // two waves per SIMD
-  const bool rows_fit = items_rows <= fine_waves;
-  const bool pairs_fit = !rows_fit && items_pairs <= fine_waves;
-  const bool blocks_fit = !rows_fit && !pairs_fit && items_blocks <= resident_waves;
-  for (int s = 0; s < n_stripes; ++s) {
-    const ec_program *prog = stripes[s].prog;
-    StripeDesc &d = desc[s];
-    const std::vector<uint32_t> *off = nullptr;
-    if (prog->split == EC_SPLIT_ROWS || (prog->split == EC_SPLIT_AUTO && rows_fit))
-      off = prog->row_parts.empty() ? nullptr : &prog->row_part_off;
-    else if (prog->split == EC_SPLIT_PAIRS || (prog->split == EC_SPLIT_AUTO && pairs_fit))
-      off = prog->pair_parts.empty() ? nullptr : &prog->pair_part_off;
-    else if (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && blocks_fit))
-      off = prog->parts.empty() ? nullptr : &prog->part_off;
-    const uint32_t n_parts = off ? (uint32_t)off->size() : 1u;
-    for (uint32_t q = 0; q < (uint32_t)kMaxRowParts; ++q) d.part_off[q] = off && q < n_parts ? (*off)[q] : 0u;
-    const uint32_t n_tiles = (d.strip_len + kTileBytes - 1) / kTileBytes;
-    const uint32_t n_its = (n_tiles + tiles_per_item - 1) / tiles_per_item;
-    // Strips a multiple of 4 MiB apart: consecutive items from 8 distant
-    // segments of the strips (the single-stripe launch does the same).
-    const bool spread = d.strip_len % (4u << 20) == 0 && n_its % 8 == 0;
-    for (uint32_t k = 0; k < n_its; ++k) {
-      const uint32_t i = spread ? (k & 7u) * (n_its >> 3) + (k >> 3) : k;
-      for (uint32_t q = 0; q < n_parts; ++q) {  // a tile's parts side by side
-        items.push_back((uint32_t)s);
-        items.push_back(i * tiles_per_item | q << kItemPartShift);
-      }
-    }
-  }
-  if (items.size() / 2 > 0xFFFFFFFFull) return EC_ERR_UNSUPPORTED;
-  if (!disjoint_writes(reads, writes)) return EC_ERR_ARG;
+  std::vector<uint32_t> items(2 * plan.n_items);
+  std::vector<ByteRange> reads(plan.n_ranges_in), writes(plan.n_ranges_out);
+  st = batch_fill(stripes, n_stripes, plan, true, desc.data(), items.data(), reads.data(), writes.data());
+  if (st != EC_OK) return st;
   ec_status gs = grow(b, desc.size(), items.size());
   if (gs != EC_OK) return gs;
   std::copy(desc.begin(), desc.end(), b->h_desc);
@@ -227,16 +278,15 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
       hipMemcpyAsync(b->d_items, b->h_items, items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs) !=
           hipSuccess)
     return EC_ERR_DEVICE;
-  b->slots = slots;
-  b->n_items = items.size() / 2;
-  b->in_bytes = in_bytes;
-  b->out_bytes = out_bytes;
+  b->slots = plan.slots;
+  b->n_items = plan.n_items;
+  b->in_bytes = plan.in_bytes;
+  b->out_bytes = plan.out_bytes;
   b->args.stripes = b->d_desc;
   b->args.items = b->d_items;
   b->args.n_items = (uint32_t)b->n_items;
-  b->args.tiles_per_item = tiles_per_item;
-  b->grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)b->n_cus * waves_per_simd(b->slots),
-                                                      (b->n_items + 3) / 4));
+  b->args.tiles_per_item = plan.tiles_per_item;
+  b->grid = batch_grid(plan, b->n_cus);
   // One item per atomic add: waves running side by side then work on
   // neighbouring tiles, which the memory system rewards more than larger
   // chunks save on the adds (measured on the 8192-stripe mix: 12.2 ms with

@@ -58,6 +58,16 @@ struct ec_program {
     stages_built = true;
   }
 
+  // The device copy of the bytecode on the current device, or null if it has
+  // not been uploaded there (allocates nothing).
+  const uint32_t *device_words_present() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = dev_words.find(dev);
+    return it == dev_words.end() ? nullptr : it->second;
+  }
+
   // Device copy of the bytecode for the current device (uploaded once).
   const uint32_t *device_words(ec_status *st) {
     int dev = 0;
