@@ -34,18 +34,16 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    # untimed launches before each timed run: the 64 MiB encode runs 3-10%
-    # slower over its first ~50 launches than from the 200th on (a warm-up
-    # with other kernels does not shorten this), and the ramp repeats after
-    # half a second idle
-    ap.add_argument("--warmup", type=int, default=300)
+    # untimed launches of the timed kernel before each timed run (after the
+    # copies of prewarm())
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--block-mib", type=int, default=64)
     ap.add_argument("--slots", type=int, default=0, help="slot budget of the compressed program (0 = default)")
     ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
     ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve",
-                                       "decode_all", "codecs", "small"],
+                                       "decode_all", "codecs", "small", "schedulers"],
                     default="all",
                     help="time one kernel only (for profiler runs)")
     ap.add_argument("--calib", action="store_true",
@@ -68,10 +66,39 @@ def log(msg):
     print("bench.py: %s" % msg, file=sys.stderr, flush=True)
 
 
-def time_launches(fn, steps, warmup, stream):
-    """Average ms per launch over `steps` back-to-back launches, bracketed by
-    HIP events on the stream the kernels run on."""
+# Device time spent on copy kernels right before each timed run's warm-up
+# launches.  After 20 ms or more without work the GPU runs HBM-bound kernels
+# up to 8% slower for the first ~15 ms of renewed load, whatever the kernel
+# (the first launches after copies or matrix products that fill that window
+# already run at full speed); the timed launches are meant to show the
+# kernel, not that transition, which "cold_ms_per_step" reports separately.
+PREWARM_MS = 50.0
+_prewarm_bufs = []
+
+
+def prewarm(stream, ms=PREWARM_MS):
+    """Queue about `ms` of back-to-back device copies of 256 MiB on `stream`
+    (no host synchronisation, so the launches that follow start with the
+    device busy).  Returns the queued copies' estimated device time."""
     import torch
+    import paper_2108_02692_amd as E
+    if ms <= 0:
+        return 0.0
+    if not _prewarm_bufs:
+        _prewarm_bufs.extend(torch.empty(256 << 20, dtype=torch.uint8, device="cuda") for _ in range(2))
+    src, dst = _prewarm_bufs
+    per_ms = 2 * src.numel() / 5.0e9  # at ~5 TB/s
+    for _ in range(max(1, int(ms / per_ms))):
+        E.ec_device_copy(dst, src, src.numel(), stream)
+    return ms
+
+
+def time_launches(fn, steps, warmup, stream, prewarm_ms=PREWARM_MS):
+    """Average ms per launch over `steps` back-to-back launches, bracketed by
+    HIP events on the stream the kernels run on, after `prewarm_ms` of
+    device copies and `warmup` untimed launches."""
+    import torch
+    prewarm(stream, prewarm_ms)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -193,12 +220,22 @@ def main():
                                       "open": pr.info["peak_open"]}), flush=True)
         return
 
+    if args.only == "schedulers":
+        print(json.dumps({"schedulers": bench_schedulers(args, stream, gen, data, parity)}), flush=True)
+        return
     res = {}
     if args.only in ("all", "compressed"):
         res["compressed"] = measure(comp, data, parity)
     if args.only in ("all", "plain"):
         res["plain"] = measure(plain, data, parity)
     log("encode timed: %s" % res)
+    cold = None
+    if args.only == "all":
+        # the same launches timed after 0.2 s idle with no copies before the
+        # warm-up launches: what a run starting from an idle GPU sees
+        time.sleep(0.2)
+        cold = time_launches(lambda: E.ec_encode(comp, data, parity, S, stream), args.steps, args.warmup, stream,
+                             prewarm_ms=0)
     extra = {}
     if args.only in ("all", "decode"):
         # decode of 4 lost data blocks (the paper's decode example erases 4)
@@ -238,6 +275,9 @@ def main():
         print(json.dumps(extra), flush=True)
         return
 
+    if args.only == "all":
+        log("strip schedulers ...")
+        extra["schedulers"] = bench_schedulers(args, stream, gen, data, parity)
     head = "compressed" if "compressed" in res else "plain"
     hprog = comp if head == "compressed" else plain
     ms = res[head]
@@ -272,6 +312,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(hprog),
                      "kernel": "slp_exec_kernel_%d" % info["slots"]},
     }
+    out["prewarm"] = {"ms": PREWARM_MS, "kernel": "ec_device_copy, 256 MiB per launch",
+                      "when": "before every timed run's warm-up launches"}
+    if cold is not None:
+        out["cold_ms_per_step"] = cold
+        out["cold_hbm_frac"] = moved / cold / 1e6 / HBM_PEAK_GBS
     if "plain" in res and head == "compressed":
         pms = res["plain"]
         out["plain"] = {"ms": pms, "GB_s": in_bytes / pms / 1e6, "hbm_frac": moved / pms / 1e6 / HBM_PEAK_GBS,
@@ -307,6 +352,41 @@ def main():
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_block_mib)
     print(json.dumps(out), flush=True)
+
+
+def bench_schedulers(args, stream, gen, data, parity):
+    """The two strip orders (EC_SCHED_PUSH, EC_SCHED_GREEDY) at the
+    compressed and the plain level, on the RS(10,4) encode of 10 x 64 MiB
+    (the data above), the decode of {2, 4, 5, 6} at that size, and the
+    encode of 10 x 1 MiB, through the single-stripe autotuner (every
+    candidate timed, the fastest reported as its choice)."""
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import autotune
+    from paper_2108_02692_amd import workloads as W
+    n, p = 10, 4
+    S = data[0].numel()
+    timer = (lambda f: time_launches(f, args.steps, args.warmup, stream))
+    name = {E.SCHED_PUSH: "push", E.SCHED_GREEDY: "greedy"}
+    rows = []
+    small = W.device_blocks(n, 1 << 20, seed=0)
+    small_par = W.empty_blocks(p, 1 << 20)
+    dec = E.ec_compile_slp(n, p, gen, [2, 4, 5, 6])
+    E.ec_encode(E.ec_compile_slp(n, p, gen), data, parity, S, stream)
+    blocks = data + parity
+    rec = W.empty_blocks(4, S)
+    cases = (("RS(10,4) encode 10 x 64 MiB", (), data, parity, S),
+             ("RS(10,4) decode {2,4,5,6} 10 x 64 MiB", (2, 4, 5, 6), [blocks[i] for i in dec.in_blocks], rec, S),
+             ("RS(10,4) encode 10 x 1 MiB", (), small, small_par, 1 << 20))
+    for what, er, ins, outs, bb in cases:
+        best, table = autotune.tune_stripe(n, p, gen, er, ins, outs, bb, stream, retune=True, time_fn=timer)
+        moved = (n + len(outs)) * bb
+        rows.append({"workload": what, "choice": {"level": best["level"], "scheduler": name[best["scheduler"]]},
+                     "candidates": [{"level": r["level"], "scheduler": name[r["scheduler"]], "slots": r["slots"],
+                                     "ms": r["ms"], "hbm_frac": moved / r["ms"] / 1e6 / HBM_PEAK_GBS,
+                                     "records": r["records"], "ops": r["ops"]} for r in table]})
+        log("%s: %s" % (what, ", ".join("%s/%s %.4f ms" % (r["level"], name[r["scheduler"]], r["ms"])
+                                         for r in table)))
+    return rows
 
 
 def worst_erasures(n, p, gen):
@@ -418,13 +498,14 @@ def bench_batched(args, stream):
     key = "mix4-%d-%dMiB" % (args.batch_stripes, args.batch_max_mib)
     best, table = autotune.tune(key, specs, inputs, outputs, stream, retune=args.retune,
                                 log=lambda r: log("autotune %s" % r))
-    cache = batching.ProgramCache(level=best["level"], slots=best["slots"])
+    cache = batching.ProgramCache(level=best["level"], slots=best["slots"], scheduler=best.get("scheduler", 0))
     cache.warm({(s.n, s.p, s.erased) for s in specs})
     batch = batching.build_batch(specs, cache, inputs, outputs, tile_bytes=best["tile_bytes"], stream=stream)
     ms = autotune.time_batch(batch, stream, steps=max(3, args.steps // 2), warmup=1)
     res = {"stripes": len(specs), "work_items": batch.n_items, "in_bytes": in_bytes, "out_bytes": out_total,
            "ms": ms, "GB_s": in_bytes / ms / 1e6, "hbm_frac": (in_bytes + out_total) / ms / 1e6 / HBM_PEAK_GBS,
            "level": best["level"], "slots": best["slots"], "tile_bytes": best["tile_bytes"],
+           "scheduler": "greedy" if best.get("scheduler", 0) else "push",
            "programs": len(cache), "graph": True}
     if table:
         res["autotune"] = table

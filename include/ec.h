@@ -74,6 +74,21 @@ enum {
 /* Compression algorithm for levels >= EC_LEVEL_CO. */
 enum { EC_COMPRESS_XORREPAIR = 0, EC_COMPRESS_REPAIR = 1 };
 
+/* Order in which the executor brings in the input strips (Sec. 6: the
+ * schedule of a straight-line program under a bounded cache; here the cache
+ * is the register slots).  Temporaries complete as their last source
+ * arrives, and the slot schedule is the same for both. */
+enum {
+  EC_SCHED_PUSH = 0,   /* level EC_LEVEL_CO_FU_SCHED: within each column block, the strip that
+                          opens the fewest temporaries net of those it completes next; lower
+                          levels: strip order (default) */
+  EC_SCHED_GREEDY = 1  /* every level: the order in which the bottom-up greedy heuristic of
+                          Sec. 6.6, run on the program's statements for an LRU cache of
+                          slot-budget entries, first reads the strips (within each column block
+                          from level EC_LEVEL_CO on); the row-split parts take the order the
+                          heuristic gives the plain rows */
+};
+
 typedef struct {
   uint32_t level;        /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
   uint32_t slot_budget;  /* register slots per lane (16 B each); supported: 24, 32, 36, 38, 40,
@@ -89,6 +104,7 @@ typedef struct {
                             the L2 cache; 0 = none (NULL opts: the library's default) */
   uint32_t split;        /* EC_SPLIT_*: whether a launch may run the output rows of one
                             tile on different waves (see ec_program_info.n_parts) */
+  uint32_t scheduler;    /* EC_SCHED_*; default EC_SCHED_PUSH */
 } ec_compile_opts;
 
 /* Row split.  Unless compiled with EC_SPLIT_NEVER, a program also carries
@@ -139,6 +155,7 @@ typedef struct {
   uint32_t n_parts;     /* block parts for the row split (0: none, e.g. one output block) */
   uint32_t n_row_parts; /* row parts for the row split (0: none) */
   uint32_t n_pair_parts; /* pair parts for the row split (0: none) */
+  uint32_t scheduler;   /* EC_SCHED_* the strip order was made with */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
 } ec_program_info;
@@ -172,14 +189,26 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
  * measures).  The arrays in *out stay valid until ec_program_free. */
 ec_status ec_program_query(const ec_program *prog, ec_program_info *out);
 
-/* Encode: data = n device pointers (blocks 0..n-1), parity = p device
- * pointers (blocks n..n+p-1), each block_bytes long.  prog must be an
- * encode program.  Parity buffers must not alias data buffers. */
+/* Encode (Sec. 1: the codeword is the generator times the data, so the
+ * parity blocks are P times the n data blocks, computed here as the
+ * program's XORs of bitmatrix rows over the strips): data = n device
+ * pointers (blocks 0..n-1), parity = p device pointers (blocks n..n+p-1),
+ * each block_bytes long, caller-owned.  prog must be an encode program
+ * (EC_ERR_ARG otherwise).  Parity buffers must not overlap each other or any
+ * data buffer (EC_ERR_ARG).  Asynchronous on `stream`; EC_ERR_ALIGN,
+ * EC_ERR_UNSUPPORTED (strips of 512 MiB or more), EC_ERR_NOMEM / EC_ERR_DEVICE
+ * on the program's first upload to the device or a failed launch. */
 ec_status ec_encode(const ec_program *prog, const uint8_t *const *data, uint8_t *const *parity,
                     size_t block_bytes, ec_stream stream);
 
-/* Decode: survivors = n device pointers in the order info.in_blocks;
- * recovered = n_erased device pointers in the order info.out_blocks. */
+/* Decode (Sec. 1: with M the rows of the generator for n surviving blocks,
+ * the data is M^-1 times the survivors, and an erased block e is row e of
+ * the generator times that; the program applies these rows, fixed at
+ * compile time, to the survivors): survivors = n device pointers in the
+ * order info.in_blocks; recovered = n_erased device pointers in the order
+ * info.out_blocks, each block_bytes long, caller-owned.  prog must be a
+ * decode program (EC_ERR_ARG otherwise); same buffer rules and errors as
+ * ec_encode. */
 ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uint8_t *const *recovered,
                     size_t block_bytes, ec_stream stream);
 

@@ -22,12 +22,13 @@ __all__ = [
     "Server", "ec_server_create",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
-    "SPLIT_ROWS", "SPLIT_PAIRS",
+    "SPLIT_ROWS", "SPLIT_PAIRS", "SCHED_PUSH", "SCHED_GREEDY",
 ]
 
 LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
 COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
 SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS, SPLIT_ROWS, SPLIT_PAIRS = 0, 1, 2, 3, 4
+SCHED_PUSH, SCHED_GREEDY = 0, 1
 STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
 
 STATUS = {
@@ -51,14 +52,14 @@ DEFAULT_PREFETCH = 0
 class CompileOpts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("slot_budget", ctypes.c_uint32),
                 ("compress", ctypes.c_uint32), ("block_strips", ctypes.c_uint32),
-                ("prefetch", ctypes.c_uint32), ("split", ctypes.c_uint32)]
+                ("prefetch", ctypes.c_uint32), ("split", ctypes.c_uint32), ("scheduler", ctypes.c_uint32)]
 
 
 class ProgramInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
         "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts",
-        "n_row_parts", "n_pair_parts")] + [
+        "n_row_parts", "n_pair_parts", "scheduler")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
 
 
@@ -278,11 +279,11 @@ class Program:
 
 def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
                    compress: int = COMPRESS_XORREPAIR, block_strips: int = 0,
-                   prefetch: int | None = None, split: int = SPLIT_AUTO) -> Program:
+                   prefetch: int | None = None, split: int = SPLIT_AUTO, scheduler: int = SCHED_PUSH) -> Program:
     er = list(erased)
     er_arr = (ctypes.c_int * max(1, len(er)))(*er)
     opts = CompileOpts(level, slot_budget, compress, block_strips,
-                       DEFAULT_PREFETCH if prefetch is None else prefetch, split)
+                       DEFAULT_PREFETCH if prefetch is None else prefetch, split, scheduler)
     h = ctypes.c_void_p()
     _check(lib().ec_compile_slp(n, p, _flat_gen(gen, n, p), er_arr, len(er), ctypes.byref(opts), ctypes.byref(h)),
            "ec_compile_slp")

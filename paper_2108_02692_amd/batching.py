@@ -16,7 +16,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import LEVEL_PLAIN, ec_batch_build, ec_compile_slp, ec_matrix_cauchy
+from . import LEVEL_PLAIN, SCHED_PUSH, ec_batch_build, ec_compile_slp, ec_matrix_cauchy
 
 CODECS_DEFAULT = ((6, 3), (10, 4), (12, 4), (14, 4))
 
@@ -40,13 +40,14 @@ class StripeSpec:
 
 
 class ProgramCache:
-    """Compiled programs keyed by (n, p, erased, level, slots); thread-safe.
-    The generator of each codec is ``generator_fn(n, p)`` ((n+p) x n rows),
-    by default the library's Cauchy matrix."""
+    """Compiled programs keyed by (n, p, erased, level, slots, scheduler);
+    thread-safe.  The generator of each codec is ``generator_fn(n, p)``
+    ((n+p) x n rows), by default the library's Cauchy matrix."""
 
-    def __init__(self, level: int = LEVEL_PLAIN, slots: int = 40, generator_fn=None):
+    def __init__(self, level: int = LEVEL_PLAIN, slots: int = 40, generator_fn=None, scheduler: int = SCHED_PUSH):
         self.level = level
         self.slots = slots
+        self.scheduler = scheduler
         self._gen_fn = generator_fn or ec_matrix_cauchy
         self._progs = {}
         self._gens = {}
@@ -60,12 +61,12 @@ class ProgramCache:
             return g
 
     def get(self, n, p, erased=()):
-        key = (n, p, tuple(erased), self.level, self.slots)
+        key = (n, p, tuple(erased), self.level, self.slots, self.scheduler)
         with self._lock:
             prog = self._progs.get(key)
         if prog is None:
             prog = ec_compile_slp(n, p, self.generator(n, p), list(erased), level=self.level,
-                                  slot_budget=self.slots)
+                                  slot_budget=self.slots, scheduler=self.scheduler)
             with self._lock:
                 prog = self._progs.setdefault(key, prog)
         return prog

@@ -182,9 +182,11 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     for (int j = 0; j < i; ++j)
       if (erased[j] == erased[i]) return EC_ERR_ARG;
   }
-  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0, kDefaultPrefetch};
+  ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0, kDefaultPrefetch, EC_SPLIT_AUTO,
+                    EC_SCHED_PUSH};
   if (opts) o = *opts;
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
+  if (o.scheduler > EC_SCHED_GREEDY) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
   if (o.split > EC_SPLIT_PAIRS) return EC_ERR_UNSUPPORTED;
@@ -218,6 +220,17 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
 
   // The executed program, in push form.
   const int width = o.block_strips ? (int)o.block_strips : 8;
+  const bool greedy = o.scheduler == EC_SCHED_GREEDY;
+  // The strip order: the push orderer at level CO_FU_SCHED, made once per
+  // program; or the bottom-up greedy heuristic of Sec. 6.6 with the slot
+  // budget k as its cache (within column blocks when there are
+  // temporaries), made for each budget tried.
+  auto order = [&](PushDag &dg, int k) {
+    if (greedy) push_order_greedy(dg, o.level >= EC_LEVEL_CO ? width : 0, k);
+  };
+  auto push_ordered = [&](PushDag &dg) {
+    if (!greedy && o.level >= EC_LEVEL_CO_FU_SCHED) push_order(dg, width);
+  };
   PushDag dag;
   if (o.level == EC_LEVEL_PLAIN) {
     dag = push_plain(brows, n_const);
@@ -225,7 +238,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     dag = push_blocked(brows, n_const, width, o.compress == EC_COMPRESS_XORREPAIR, o.level >= EC_LEVEL_CO_FU);
     if (o.level >= EC_LEVEL_CO_FU_SCHED) {
       push_unfold(dag, kRecordCost);
-      push_order(dag, width);
+      push_ordered(dag);
     }
   }
   PushOpts po;
@@ -233,6 +246,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   auto place = [&]() -> int {
     if (o.slot_budget) {
       po.slots = (int)o.slot_budget;
+      order(dag, po.slots);
       return push_schedule(dag, n_in, po, prog->code);
     }
     // The budgets that set the executor's occupancy (4, 3 and 2 waves per
@@ -242,6 +256,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     int rc = -1;
     for (uint32_t k : {24u, 32u, 38u, 44u, 48u}) {
       po.slots = (int)k;
+      order(dag, po.slots);
       rc = push_schedule(dag, n_in, po, prog->code);
       if (rc == 0 && ((prog->code.passes == 1 && prog->code.ring >= 3) || k == 48)) break;
     }
@@ -254,7 +269,8 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     for (int cost : {3, 4, 6}) {
       PushDag trial = dag;
       push_unfold(trial, cost);
-      push_order(trial, width);
+      push_ordered(trial);
+      order(trial, 38);
       PushCode code;
       PushOpts p38 = po;
       p38.slots = 38;
@@ -271,7 +287,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   for (int cost : {4, 8, 16, 64, 1 << 20}) {
     if (rc == 0 || o.level == EC_LEVEL_PLAIN) break;
     push_unfold(dag, cost);
-    if (o.level >= EC_LEVEL_CO_FU_SCHED) push_order(dag, width);
+    push_ordered(dag);
     rc = place();
   }
   if (rc != 0) return EC_ERR_CAPACITY;
@@ -300,7 +316,8 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   // no records for temporaries (measured on RS(10,4) encodes, 8 KiB - 1 MiB
   // blocks: row parts 10.5-10.8 us plain against 11.8-12.1 us compressed,
   // block parts 20.2-20.7 against 22.3-22.9 us; 2-20% on every codec tried).
-  const PushDag pdag = o.level == EC_LEVEL_PLAIN ? dag : push_plain(brows, n_const);
+  PushDag pdag = o.level == EC_LEVEL_PLAIN ? dag : push_plain(brows, n_const);
+  if (greedy && o.level != EC_LEVEL_PLAIN) push_order_greedy(pdag, 0, po.slots);
   prog->split = (int)o.split;
   prog->image = prog->code.words;
   prog->part_off.clear();
@@ -369,6 +386,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_parts = (uint32_t)prog->parts.size();
   info.n_row_parts = (uint32_t)prog->row_parts.size();
   info.n_pair_parts = (uint32_t)prog->pair_parts.size();
+  info.scheduler = o.scheduler;
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();

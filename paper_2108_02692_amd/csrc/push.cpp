@@ -225,6 +225,24 @@ void push_order(PushDag &d, int width) {
   d.order = order;
 }
 
+void push_order_greedy(PushDag &d, int width, int capacity) {
+  const Slp g = greedy_schedule(push_as_slp(d), std::max(1, capacity));
+  std::vector<char> used(d.n_const, 0), seen(d.n_const, 0);
+  for (int c : d.order) used[c] = 1;
+  std::vector<int> first;
+  for (const Stmt &st : g.stmts)
+    for (int o : st.ops)
+      if (is_const(o) && used[o - kConstBase] && !seen[o - kConstBase]) {
+        seen[o - kConstBase] = 1;
+        first.push_back(o - kConstBase);
+      }
+  for (int c : d.order)  // (every strip in the order has a consumer, so none is left)
+    if (!seen[c]) first.push_back(c);
+  if (width > 0)
+    std::stable_sort(first.begin(), first.end(), [width](int a, int b) { return a / width < b / width; });
+  d.order = first;
+}
+
 std::vector<Bits> push_eval(const PushDag &d) {
   std::vector<Bits> val(d.src.size());
   std::vector<char> done(d.src.size(), 0);

@@ -51,6 +51,15 @@ void push_unfold(PushDag &d, int record_cost);
 // lower strip).
 void push_order(PushDag &d, int width);
 
+// Orders the strips by the bottom-up greedy heuristic of Sec. 6.6: the
+// program in statement form (push_as_slp) is scheduled for an LRU cache of
+// `capacity` entries (the register slots), and the strips are brought in in
+// the order that schedule first reads them.  With width > 0 the column
+// blocks keep their order (a temporary combines strips of one block only, so
+// interleaving blocks would only hold temporaries open longer) and the
+// greedy order applies within each block.
+void push_order_greedy(PushDag &d, int width, int capacity);
+
 // Set-semantics value of every row.
 std::vector<Bits> push_eval(const PushDag &d);
 

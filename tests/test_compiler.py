@@ -18,7 +18,7 @@ import pytest
 import oracle
 from oracle import slp as S
 import paper_2108_02692_amd as E
-from bytecode_sim import simulate
+from bytecode_sim import fields, simulate
 
 BIG = S.Compressed.BIG
 
@@ -182,6 +182,70 @@ def test_bytecode_simulates_to_bitmatrix(level, K):
         assert prog.info["n_stores"] == len(rows)
         assert prog.info["slots"] == K
         assert prog.info["n_loads"] == 80 * prog.info["passes"]
+
+
+def load_order(words):
+    """Input strips in the order the records load them (LOAD and INPUT_LD
+    records; strip 8 * block + j)."""
+    out, pc = [], 0
+    while pc < len(words):
+        f = fields(words[pc], words[pc + 1])
+        if f["kind"] == 6:  # HALT
+            break
+        if f["kind"] in (2, 5):
+            out.append(8 * f["blk"] + f["j"])
+        pc += f["bytes"] // 4
+    return out
+
+
+def greedy_first_reads(stmts, outs, capacity, width):
+    """The order in which the oracle's bottom-up greedy heuristic (Sec. 6.6)
+    first reads the input strips of a program, for an LRU cache of
+    `capacity` entries; with width > 0, stable by column block."""
+    st, ou = to_oracle_terms(stmts, outs)
+    isc = lambda t: isinstance(t, int) and t >= BIG
+    peb, _, _ = S.greedy_schedule(st, ou, isc, capacity)
+    seen = []
+    for _, args in peb:
+        for a in args:
+            if isc(a) and a - BIG not in seen:
+                seen.append(a - BIG)
+    return sorted(seen, key=lambda c: c // width) if width else seen
+
+
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
+def test_greedy_scheduler_programs(level, K):
+    """EC_SCHED_GREEDY at every level and slot budget: the records compute
+    the bitmatrix rows (independent simulator), and a single-pass program
+    loads the strips in the order the oracle's greedy heuristic first reads
+    them in the program's statements, with the slot budget as the cache."""
+    n, p = 10, 4
+    gen = E.ec_matrix_cauchy(n, p)
+    for er in sample_patterns(n, p, 2, 3 * K + level):
+        prog = E.ec_compile_slp(n, p, gen, er, level=level, slot_budget=K, scheduler=E.SCHED_GREEDY)
+        assert prog.info["scheduler"] == E.SCHED_GREEDY
+        rows = oracle_rows(gen, n, p, er)
+        stmts, outs = prog.export(E.STAGE_EXEC)
+        assert eval_export(stmts, outs) == rows
+        got = simulate(prog.bytecode(), K, n, len(prog.out_blocks))
+        assert [got[o] for o in range(len(rows))] == rows
+        for k in range(prog.info["n_parts"] + prog.info["n_row_parts"] + prog.info["n_pair_parts"]):
+            part = simulate(prog.part_bytecode(k), K, n, len(prog.out_blocks))
+            assert all(part[o] == rows[o] for o in part)
+        if prog.info["passes"] == 1:
+            want = greedy_first_reads(stmts, outs, K, 8 if level >= E.LEVEL_CO else 0)
+            assert load_order(prog.bytecode()) == want
+
+
+def test_schedulers_differ_and_default_is_push():
+    gen = E.ec_matrix_cauchy(10, 4)
+    push = E.ec_compile_slp(10, 4, gen, level=E.LEVEL_CO_FU)
+    greedy = E.ec_compile_slp(10, 4, gen, level=E.LEVEL_CO_FU, scheduler=E.SCHED_GREEDY)
+    assert push.info["scheduler"] == E.SCHED_PUSH
+    assert load_order(push.bytecode()) != load_order(greedy.bytecode())
+    with pytest.raises(E.EcError, match="EC_ERR_UNSUPPORTED"):
+        E.ec_compile_slp(10, 4, gen, scheduler=2)
 
 
 @pytest.mark.parametrize("n,p", [(6, 3), (12, 4), (14, 4)])

@@ -1,7 +1,7 @@
 """Every output byte of the benchmarked configurations against the oracle.
 
 * RS(10,4) encode of 10 x 64 MiB blocks (both program levels the benchmark
-  times) and the decode of erasure sets at that size: every byte, the oracle
+  times, under both strip schedulers) and the decode of erasure sets at that size: every byte, the oracle
   running on host threads over disjoint strip-offset ranges.  At 64 MiB the
   executor takes tiles from 8 distant segments of the strips (strips 4 MiB
   apart or a multiple of it); a smaller codec at 32 MiB blocks (4 MiB
@@ -9,7 +9,7 @@
   batch.
 * The 8192-stripe batched mix of the benchmark (four codecs, blocks of
   4 KiB - 4 MiB, 70% encodes), under every (level, slot budget, work-item
-  width) the autotuner chooses between: every output byte of every stripe
+  width, strip scheduler) the autotuner chooses between: every output byte of every stripe
   through the bitmatrix relation of ``strip_check`` (the oracle's
   bitmatrix), and a
   seeded subset of stripes, with the largest block of each codec and
@@ -60,10 +60,11 @@ def rs10_4_64mib():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("level", [E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN])
-def test_encode_64mib_every_byte(rs10_4_64mib, level):
+@pytest.mark.parametrize("level,sched", [(E.LEVEL_CO_FU_SCHED, E.SCHED_PUSH), (E.LEVEL_PLAIN, E.SCHED_PUSH),
+                                         (E.LEVEL_CO_FU_SCHED, E.SCHED_GREEDY), (E.LEVEL_PLAIN, E.SCHED_GREEDY)])
+def test_encode_64mib_every_byte(rs10_4_64mib, level, sched):
     n, p, S, G, data, host, want = rs10_4_64mib
-    prog = E.ec_compile_slp(n, p, gen_rows(n, p), level=level)
+    prog = E.ec_compile_slp(n, p, gen_rows(n, p), level=level, scheduler=sched)
     out = W.empty_blocks(p, S, fill=0xA5)
     E.ec_encode(prog, data, out, S)
     torch.cuda.synchronize()
@@ -172,10 +173,10 @@ def mix8192():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("level,slots,tile", autotune.DEFAULT_CANDIDATES)
-def test_batch_8192_mix_every_byte(mix8192, level, slots, tile):
+@pytest.mark.parametrize("level,slots,tile,sched", autotune.DEFAULT_CANDIDATES)
+def test_batch_8192_mix_every_byte(mix8192, level, slots, tile, sched):
     specs, inputs, outputs, out_buf, pool_h, offs, M, fins, matrix = mix8192
-    cache = B.ProgramCache(level=level, slots=slots, generator_fn=oracle.cauchy)
+    cache = B.ProgramCache(level=level, slots=slots, generator_fn=oracle.cauchy, scheduler=sched)
     cache.warm({(s.n, s.p, s.erased) for s in specs})
     stream = torch.cuda.current_stream()
     batch = B.build_batch(specs, cache, inputs, outputs, tile_bytes=tile, stream=stream)

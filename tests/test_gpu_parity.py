@@ -83,6 +83,27 @@ def test_encode_rs10_4_1mib(level, K):
     assert_blocks_equal(run_encode(prog, data, S), want, "encode level %d K %d" % (level, K))
 
 
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
+def test_greedy_scheduler_rs10_4(level, K):
+    """Programs whose strip order comes from the bottom-up greedy heuristic
+    (EC_SCHED_GREEDY): RS(10,4) encode and the decode of {2, 4, 5, 6} on
+    1 MiB blocks (pair parts) and on 4 MiB + 128 B blocks (whole program,
+    ragged last tile), every level and slot budget."""
+    n, p = 10, 4
+    gen = oracle_gen(n, p)
+    G = np.array(gen, dtype=np.uint8)
+    er = [2, 4, 5, 6]
+    for S in (1 << 20, (4 << 20) + 128):
+        data = W.host_blocks(n, S, seed=K + level)
+        blocks = data + oracle.encode(G, n, p, data)
+        enc = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K, scheduler=E.SCHED_GREEDY)
+        assert_blocks_equal(run_encode(enc, data, S), blocks[n:], "greedy encode level %d K %d S %d" % (level, K, S))
+        dec = E.ec_compile_slp(n, p, gen, er, level=level, slot_budget=K, scheduler=E.SCHED_GREEDY)
+        assert_blocks_equal(run_decode(dec, blocks, S), [blocks[e] for e in er],
+                            "greedy decode level %d K %d S %d" % (level, K, S))
+
+
 @pytest.mark.parametrize("S", [128, 256, 1152, 8192 + 128, 3 * 8192, 65536 + 640])
 def test_encode_ragged_sizes(S):
     """Block sizes that leave a partial tile (1 KiB per strip per wave)."""
