@@ -268,6 +268,15 @@ def main():
             copy()
             torch.cuda.synchronize()
         del src, dst
+    if args.only in ("all", "copy"):
+        # the encode's own data movement (10 blocks read, 4 written, same
+        # tile order) with no program: the ceiling for this access pattern
+        ms_stream = time_launches(lambda: E.ec_stripe_stream(data, parity, S, stream), args.steps, args.warmup,
+                                  stream)
+        extra["stripe_ceiling"] = {"ms": ms_stream, "GB_s": moved / ms_stream / 1e6,
+                                   "hbm_frac": moved / ms_stream / 1e6 / HBM_PEAK_GBS,
+                                   "what": "ec_stripe_stream: 10 x %d MiB read, 4 x %d MiB written, executor tile "
+                                           "order, no program" % (args.block_mib, args.block_mib)}
     if args.only == "copy":
         print(json.dumps(extra), flush=True)
         return
@@ -326,6 +335,8 @@ def main():
     out.update(extra)
     if "copy_ceiling_GB_s" in out:
         out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GB_s"]
+    if "stripe_ceiling" in out:
+        out["roofline"]["frac_of_stripe_ceiling"] = achieved / out["stripe_ceiling"]["GB_s"]
     if args.only == "all":
         del data, parity
         torch.cuda.empty_cache()
@@ -345,7 +356,7 @@ def main():
         torch.cuda.empty_cache()
     if args.only == "all" and args.serve_seconds > 0:
         log("serving ...")
-        out["serving"] = bench_serving(args)
+        out["serving"] = bench_serving(args, out.get("batched", {}).get("GB_s"))
         log("serving: p50 %.3f ms p99 %.3f ms" % (out["serving"]["p50_ms"], out["serving"]["p99_ms"]))
         torch.cuda.empty_cache()
     if not args.no_cpu:
@@ -470,17 +481,31 @@ def bench_small(args, stream):
     return res
 
 
-def bench_serving(args):
+def bench_serving(args, batched_GB_s=None):
     """The serving loop on 20k req/s Poisson arrivals, ``--serve-runs`` times
     (the host can interrupt the loop's thread, which moves p99 from run to
-    run): medians of the latency and drain figures, every run's in 'runs'."""
+    run): medians of the latency and drain figures, every run's in 'runs';
+    then a sweep of arrival rates (about 40,000 requests each) up to the
+    drain, where every request is present at once."""
     import numpy as np
     from paper_2108_02692_amd import serve
-    runs = [serve.run(duration_s=args.serve_seconds, seed=7) for _ in range(max(1, args.serve_runs))]
+    server = serve.Server()
+    runs = [serve.run(duration_s=args.serve_seconds, seed=7, server=server) for _ in range(max(1, args.serve_runs))]
     res = dict(runs[0])
-    for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s"):
+    for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s", "requests_per_launch"):
         res[k] = float(np.median([r[k] for r in runs]))
-    res["runs"] = [{k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s")} for r in runs]
+    res["runs"] = [{k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s", "requests_per_launch")}
+                   for r in runs]
+    sweep = []
+    for rate in (20e3, 100e3, 500e3, 2e6, 8e6):
+        r = serve.run(duration_s=40000.0 / rate, rate=rate, seed=8, server=server, drain=False)
+        sweep.append({k: r[k] for k in ("rate_req_s", "requests", "GB_s", "p50_ms", "p99_ms", "mean_ms",
+                                        "requests_per_launch", "batches")})
+        log("serving at %.0f req/s: %.1f GB/s, p50 %.3f ms, p99 %.3f ms, %.1f requests per launch"
+            % (rate, r["GB_s"], r["p50_ms"], r["p99_ms"], r["requests_per_launch"]))
+    res["sweep"] = sweep
+    if batched_GB_s:
+        res["drain_vs_batched"] = res["drain_GB_s"] / batched_GB_s
     return res
 
 

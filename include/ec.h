@@ -256,12 +256,24 @@ ec_status ec_program_export(const ec_program *prog, int stage, int32_t *buf, siz
  * a program of level >= EC_LEVEL_CO_FU (else EC_ERR_ARG).  Host-only. */
 ec_status ec_program_export_greedy(const ec_program *prog, int capacity, int32_t *buf, size_t cap, size_t *len);
 
-/* Device-to-device copy with a plain 16-byte-per-lane kernel: the HBM
- * bandwidth ceiling that executor throughput is compared with, and the
+/* ---- bandwidth references (not part of the paper's method)
+ *
+ * Device-to-device copy (non-temporal 16-byte accesses, two per lane per
+ * step, 16 workgroups per compute unit): the plain HBM copy ceiling, and the
  * kernel used to calibrate byte counters.  bytes: multiple of 16; both
  * pointers 16-byte aligned (EC_ERR_ALIGN) and not overlapping (EC_ERR_ARG).
  * Asynchronous on `stream`. */
 ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream stream);
+
+/* The data movement of one ec_encode / ec_decode launch without a program:
+ * every tile (1 KiB of every strip) reads all n_in input blocks' strips and
+ * writes all n_out output blocks' strips, in the executor's tile order, each
+ * output strip-tile being the XOR of that tile's n_in * 8 input strip-tiles
+ * (a stand-in that needs every input byte).  The ceiling for a coding launch
+ * of the same shape.  Same block rules and errors as ec_encode; needs
+ * n_in >= 1, n_out >= 0, n_in + n_out <= 32 (EC_ERR_ARG). */
+ec_status ec_stripe_stream(const uint8_t *const *in, int n_in, uint8_t *const *out, int n_out, size_t block_bytes,
+                           ec_stream stream);
 
 /* The device bytecode the executor runs per tile (host copy). */
 ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, size_t *n_words);
@@ -365,9 +377,10 @@ ec_status ec_batch_run_noalloc(const ec_stripe *stripes, int n_stripes, size_t t
  * the programs above.  ec_server_run admits arrived requests, in arrival
  * order, while their input + output bytes fit budget_bytes (counting every
  * request in flight) and their outputs fit a first-fit arena in the
- * caller's device buffer; spreads the arrived requests over the free slots
- * and packs each slot's share (up to max_batch, of one slot budget) into one
- * launch on that slot's stream, a plain
+ * caller's device buffer; spreads the arrived requests' work (their bytes
+ * read and written) evenly over the free slots and packs each slot's share
+ * (in arrival order, at least one request and at most max_batch, of one
+ * slot budget) into one launch on that slot's stream, a plain
  * ec_encode / ec_decode launch for one request and a reusable ec_batch for
  * more; and keeps admitting while earlier launches run, so requests
  * admitted meanwhile overlap with them on the device.  Completion is found
@@ -377,8 +390,8 @@ ec_status ec_batch_run_noalloc(const ec_stripe *stripes, int n_stripes, size_t t
 typedef struct {
   double arrival_s;          /* arrival, seconds after the run starts; nondecreasing over a run */
   const ec_program *prog;    /* encode or decode program */
-  const uint8_t *const *in;  /* prog's n_in device input pointers (info.in_blocks order); they
-                                must not overlap any output placed in the arena */
+  const uint8_t *const *in;  /* prog's n_in device input pointers (info.in_blocks order), 16-byte
+                                aligned and outside the arena (checked up front) */
   size_t block_bytes;        /* multiple of 128 */
 } ec_request;
 
@@ -411,8 +424,9 @@ ec_status ec_server_create(uint8_t *arena, size_t arena_bytes, const ec_serve_op
  * the space, or a later run's warm-up of a new slot budget writes the
  * arena's first 4 KiB); *wall_s the run's length and *n_batches the
  * launches made (out_offsets, wall_s and n_batches may be NULL).  Checked up front:
- * arrival order, sizes (EC_ERR_ALIGN), and that every request fits the
- * budget and the arena alone (EC_ERR_CAPACITY).  On a launch or device
+ * arrival order, sizes and input alignment (EC_ERR_ALIGN), inputs outside
+ * the arena (EC_ERR_ARG), and that every request fits the budget and the
+ * arena alone (EC_ERR_CAPACITY).  On a launch or device
  * error the loop waits for the work in flight and returns the error.  One
  * thread at a time per server. */
 ec_status ec_server_run(ec_server *server, const ec_request *reqs, int n_reqs, int realtime,

@@ -18,7 +18,7 @@ from . import _build
 __all__ = [
     "EcError", "Program", "ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp",
     "ec_encode", "ec_decode", "ec_status_str", "Batch", "ec_batch_build", "ec_batch_run_noalloc", "ec_device_copy",
-    "lib",
+    "ec_stripe_stream", "lib",
     "Server", "ec_server_create",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
@@ -114,6 +114,8 @@ def lib():
         L.ec_program_part_bytecode.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
                                                ctypes.POINTER(ctypes.c_size_t)]
         L.ec_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.ec_stripe_stream.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int,
+                                       ctypes.c_size_t, vp]
         L.ec_program_upload.argtypes = [vp]
         L.ec_batch_reserve.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
         L.ec_batch_build.argtypes = [ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
@@ -134,7 +136,7 @@ def lib():
         L.ec_server_free.restype = None
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
                      "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_program_part_bytecode", "ec_batch_build", "ec_device_copy",
-                     "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set",
+                     "ec_stripe_stream", "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set",
                      "ec_batch_run_noalloc",
                      "ec_server_create", "ec_server_run"):
             getattr(L, name).restype = st
@@ -308,6 +310,14 @@ def ec_device_copy(dst, src, nbytes: int, stream=None):
     _check(lib().ec_device_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)), "ec_device_copy")
 
 
+def ec_stripe_stream(inputs, outputs, block_bytes: int, stream=None):
+    """A coding launch's data movement without a program (every output
+    strip-tile = XOR of the tile's input strip-tiles): the ceiling for a
+    launch of that shape."""
+    _check(lib().ec_stripe_stream(_ptr_array(inputs), len(inputs), _ptr_array(outputs), len(outputs), block_bytes,
+                                  _stream_handle(stream)), "ec_stripe_stream")
+
+
 class Batch:
     """Owner of an ``ec_batch`` (many stripes, one persistent launch)."""
 
@@ -457,7 +467,7 @@ class Server:
             pass
 
 
-def ec_server_create(arena, arena_bytes: int, budget_bytes: int, n_slots: int = 4, max_batch: int = 512) -> Server:
+def ec_server_create(arena, arena_bytes: int, budget_bytes: int, n_slots: int = 4, max_batch: int = 2048) -> Server:
     """A native serving loop over the device arena ``arena`` (a tensor or a
     pointer; ``arena_bytes`` long): ``n_slots`` streams, launches of up to
     ``max_batch`` requests, admission within ``budget_bytes``."""

@@ -34,6 +34,7 @@ struct ec_batch {
   uint32_t *d_items = nullptr, *h_items = nullptr;
   uint32_t *d_counter = nullptr;
   size_t cap_desc = 0, cap_items = 0;
+  std::vector<ByteRange> reads, writes;  // overlap-check workspaces, reused
   BatchArgs args{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -154,8 +155,9 @@ ec_status batch_plan(const ec_stripe *stripes, int n_stripes, size_t tile_bytes,
   return EC_OK;
 }
 
-ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &plan, bool upload, StripeDesc *desc,
-                     uint32_t *items, ByteRange *reads, ByteRange *writes) {
+ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &plan, int dev, bool upload,
+                     StripeDesc *desc, uint32_t *items, ByteRange *reads, ByteRange *writes) {
+  const bool check = reads && writes;
   size_t nr = 0, nw = 0, w = 0;
   for (int s = 0; s < n_stripes; ++s) {
     const ec_stripe &st = stripes[s];
@@ -165,15 +167,15 @@ ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &p
     std::memset(&d, 0, sizeof d);  // unused block entries are zero (the kernel reads all 32)
     for (int i = 0; i < n_in; ++i) {
       d.blk[i] = (uint64_t)(uintptr_t)st.in[i];
-      reads[nr++] = {(uintptr_t)st.in[i], (uintptr_t)st.in[i] + st.block_bytes};
+      if (check) reads[nr++] = {(uintptr_t)st.in[i], (uintptr_t)st.in[i] + st.block_bytes};
     }
     for (int j = 0; j < n_out; ++j) {
       d.blk[n_in + j] = (uint64_t)(uintptr_t)st.out[j];
-      writes[nw++] = {(uintptr_t)st.out[j], (uintptr_t)st.out[j] + st.block_bytes};
+      if (check) writes[nw++] = {(uintptr_t)st.out[j], (uintptr_t)st.out[j] + st.block_bytes};
     }
     ec_program *mp = const_cast<ec_program *>(prog);
     ec_status ws = EC_OK;
-    d.prog = upload ? mp->device_words(&ws) : mp->device_words_present();
+    d.prog = upload ? mp->device_words(dev, &ws) : mp->device_words_present(dev);
     if (!d.prog) return upload ? ws : EC_ERR_ARG;
     d.n_blocks = (uint32_t)(n_in + n_out);
     d.strip_len = (uint32_t)(st.block_bytes / 8);
@@ -181,18 +183,20 @@ ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &p
     const uint32_t n_parts = off ? (uint32_t)off->size() : 1u;
     for (uint32_t q = 0; q < (uint32_t)kMaxRowParts; ++q) d.part_off[q] = off && q < n_parts ? (*off)[q] : 0u;
     const uint32_t n_its = (n_tiles_of(st.block_bytes) + plan.tiles_per_item - 1) / plan.tiles_per_item;
-    // Strips a multiple of 4 MiB apart: consecutive items from 8 distant
-    // segments of the strips (the single-stripe launch does the same).
-    const bool spread = d.strip_len % (4u << 20) == 0 && n_its % 8 == 0;
+    // Strips a multiple of 4 MiB apart: groups of 4 consecutive items on 4
+    // neighbouring tiles, consecutive groups in 8 distant segments of the
+    // strips (the single-stripe launch's tile order).
+    const bool spread = d.strip_len % (4u << 20) == 0 && n_its % 32 == 0;
     for (uint32_t k = 0; k < n_its; ++k) {
-      const uint32_t i = spread ? (k & 7u) * (n_its >> 3) + (k >> 3) : k;
+      const uint32_t g = k / 4;
+      const uint32_t i = spread ? (g & 7u) * (n_its >> 3) + (g >> 3) * 4 + k % 4 : k;
       for (uint32_t q = 0; q < n_parts; ++q) {  // a tile's parts side by side
         items[w++] = (uint32_t)s;
         items[w++] = i * plan.tiles_per_item | q << kItemPartShift;
       }
     }
   }
-  if (!disjoint_writes(reads, nr, writes, nw)) return EC_ERR_ARG;
+  if (check && !disjoint_writes(reads, nr, writes, nw)) return EC_ERR_ARG;
   return EC_OK;
 }
 
@@ -241,41 +245,33 @@ ec_status grow(ec_batch *b, size_t n_desc, size_t n_words) {
 
 }  // namespace
 
-extern "C" {
+namespace ec {
 
-ec_status ec_batch_create(ec_batch **out) {
-  if (!out) return EC_ERR_ARG;
-  *out = nullptr;
-  std::unique_ptr<ec_batch> b(new (std::nothrow) ec_batch);
-  if (!b) return EC_ERR_NOMEM;
-  if (hipGetDevice(&b->device) != hipSuccess) return EC_ERR_DEVICE;
-  if (hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
-    return EC_ERR_DEVICE;
-  if (hipMalloc((void **)&b->d_counter, 256) != hipSuccess) return EC_ERR_NOMEM;
-  *out = b.release();
-  return EC_OK;
-}
-
-ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream) {
+ec_status batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
+                    bool check_overlap) {
   if (!b || !stripes || n_stripes <= 0) return EC_ERR_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return EC_ERR_DEVICE;
   BatchPlan plan;
   ec_status st = batch_plan(stripes, n_stripes, tile_bytes, b->n_cus, &plan);
   if (st != EC_OK) return st;
-  std::vector<StripeDesc> desc((size_t)n_stripes);
-  std::vector<uint32_t> items(2 * plan.n_items);
-  std::vector<ByteRange> reads(plan.n_ranges_in), writes(plan.n_ranges_out);
-  st = batch_fill(stripes, n_stripes, plan, true, desc.data(), items.data(), reads.data(), writes.data());
+  st = grow(b, (size_t)n_stripes, 2 * plan.n_items);
   if (st != EC_OK) return st;
-  ec_status gs = grow(b, desc.size(), items.size());
-  if (gs != EC_OK) return gs;
-  std::copy(desc.begin(), desc.end(), b->h_desc);
-  std::copy(items.begin(), items.end(), b->h_items);
+  // Tables straight into the pinned staging (the previous launch of this
+  // batch, and so its copies, must have completed).
+  ByteRange *reads = nullptr, *writes = nullptr;
+  if (check_overlap) {
+    b->reads.resize(plan.n_ranges_in);
+    b->writes.resize(plan.n_ranges_out);
+    reads = b->reads.data();
+    writes = b->writes.data();
+  }
+  st = batch_fill(stripes, n_stripes, plan, dev, true, b->h_desc, b->h_items, reads, writes);
+  if (st != EC_OK) return st;
   const hipStream_t hs = (hipStream_t)stream;
-  if (hipMemcpyAsync(b->d_desc, b->h_desc, desc.size() * sizeof(StripeDesc), hipMemcpyHostToDevice, hs) !=
+  if (hipMemcpyAsync(b->d_desc, b->h_desc, (size_t)n_stripes * sizeof(StripeDesc), hipMemcpyHostToDevice, hs) !=
           hipSuccess ||
-      hipMemcpyAsync(b->d_items, b->h_items, items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, hs) !=
+      hipMemcpyAsync(b->d_items, b->h_items, 2 * plan.n_items * sizeof(uint32_t), hipMemcpyHostToDevice, hs) !=
           hipSuccess)
     return EC_ERR_DEVICE;
   b->slots = plan.slots;
@@ -296,6 +292,27 @@ ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, siz
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return EC_OK;
+}
+
+}  // namespace ec
+
+extern "C" {
+
+ec_status ec_batch_create(ec_batch **out) {
+  if (!out) return EC_ERR_ARG;
+  *out = nullptr;
+  std::unique_ptr<ec_batch> b(new (std::nothrow) ec_batch);
+  if (!b) return EC_ERR_NOMEM;
+  if (hipGetDevice(&b->device) != hipSuccess) return EC_ERR_DEVICE;
+  if (hipDeviceGetAttribute(&b->n_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
+    return EC_ERR_DEVICE;
+  if (hipMalloc((void **)&b->d_counter, 256) != hipSuccess) return EC_ERR_NOMEM;
+  *out = b.release();
+  return EC_OK;
+}
+
+ec_status ec_batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream) {
+  return batch_set(b, stripes, n_stripes, tile_bytes, stream, true);
 }
 
 ec_status ec_batch_reserve(ec_batch *b, int n_stripes, size_t n_items) {

@@ -33,16 +33,22 @@ struct BatchPlan {
 // batch_fill).
 ec_status batch_plan(const ec_stripe *stripes, int n_stripes, size_t tile_bytes, int n_cus, BatchPlan *plan);
 
-// Writes the n_stripes descriptors and the 2 * plan.n_items item words, and
-// checks that no output block overlaps another output block or any input
-// block, with reads / writes as workspaces of plan.n_ranges_in /
-// plan.n_ranges_out entries.  upload = true copies a program to the current
-// device if it is not there yet (an allocation); false makes such a program
-// an EC_ERR_ARG.
-ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &plan, bool upload, StripeDesc *desc,
-                     uint32_t *items, ByteRange *reads, ByteRange *writes);
+// Writes the n_stripes descriptors and the 2 * plan.n_items item words for
+// device `dev` (the current device), and, when reads and writes are given
+// (workspaces of plan.n_ranges_in / plan.n_ranges_out entries), checks that
+// no output block overlaps another output block or any input block.
+// upload = true copies a program to the device if it is not there yet (an
+// allocation); false makes such a program an EC_ERR_ARG.
+ec_status batch_fill(const ec_stripe *stripes, int n_stripes, const BatchPlan &plan, int dev, bool upload,
+                     StripeDesc *desc, uint32_t *items, ByteRange *reads, ByteRange *writes);
 
 // Workgroups of the persistent kernel for a plan on a device of n_cus CUs.
 int batch_grid(const BatchPlan &plan, int n_cus);
+
+// ec_batch_set; check_overlap = false skips the check that outputs overlap
+// no other output and no input (for a caller whose buffers are disjoint by
+// construction, such as the serving loop with its output arena).
+ec_status batch_set(ec_batch *b, const ec_stripe *stripes, int n_stripes, size_t tile_bytes, ec_stream stream,
+                    bool check_overlap);
 
 }  // namespace ec

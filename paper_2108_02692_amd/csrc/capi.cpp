@@ -60,10 +60,9 @@ int device_cus() {
   return n;
 }
 
-ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *const *out, size_t block_bytes,
-                 ec_stream stream) {
-  if (!prog || !in || !out) return EC_ERR_ARG;
-  const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+// Block arguments of a launch: sizes, alignment, and no output overlapping
+// an input or another output.
+ec_status check_blocks(const uint8_t *const *in, int n_in, uint8_t *const *out, int n_out, size_t block_bytes) {
   if (block_bytes == 0 || block_bytes % 128 != 0) return EC_ERR_ALIGN;
   if (block_bytes / 8 > 0x1FFFFFFFull) return EC_ERR_UNSUPPORTED;  // strip offsets must fit 32 bits
   for (int i = 0; i < n_in; ++i)
@@ -84,13 +83,14 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
       if (a < b + block_bytes && b < a + block_bytes) return EC_ERR_ARG;
     }
   }
-  ec_status st = EC_OK;
-  const uint32_t *words = const_cast<ec_program *>(prog)->device_words(&st);
-  if (!words) return st;
-  ExecArgs a{};
+  return EC_OK;
+}
+
+// Block table, strip length, tiles and tile order of a launch.
+void set_blocks(ExecArgs &a, const uint8_t *const *in, int n_in, uint8_t *const *out, int n_out,
+                size_t block_bytes) {
   for (int i = 0; i < n_in; ++i) a.blk[i] = (uint64_t)(uintptr_t)in[i];
   for (int j = 0; j < n_out; ++j) a.blk[n_in + j] = (uint64_t)(uintptr_t)out[j];
-  a.prog = words;
   a.n_in = (uint32_t)n_in;
   a.strip_len = block_bytes / 8;
   a.n_tiles = (uint32_t)((a.strip_len + kTileBytes - 1) / kTileBytes);
@@ -98,11 +98,27 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   // one tile offset collide in the memory system's address mapping and
   // waves running side by side on neighbouring tiles slow each other down
   // (measured: 52% of peak at 64 MiB blocks against 60-64% at other sizes);
-  // consecutive waves then take tiles from 8 distant segments instead.
+  // the tiles are then taken from 8 distant segments of the strips, each
+  // workgroup's 4 waves on 4 neighbouring tiles of one segment (measured on
+  // the data movement alone, 10 x 64 MiB in and 4 x 64 MiB out: 0.735 of
+  // peak against 0.728 with consecutive waves in different segments).
   a.seg_shift = 0;
-  if (a.strip_len % (4u << 20) == 0 && a.n_tiles % 8 == 0) a.seg_shift = 3;
+  if (a.strip_len % (4u << 20) == 0 && a.n_tiles % 8 == 0 && (a.n_tiles >> 3) % 4 == 0) a.seg_shift = 3;
   a.seg_mask = (1u << a.seg_shift) - 1;
   a.seg_tiles = a.n_tiles >> a.seg_shift;
+}
+
+ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *const *out, size_t block_bytes,
+                 ec_stream stream) {
+  if (!prog || !in || !out) return EC_ERR_ARG;
+  const int n_in = (int)prog->in_blocks.size(), n_out = (int)prog->out_blocks.size();
+  ec_status st = check_blocks(in, n_in, out, n_out, block_bytes);
+  if (st != EC_OK) return st;
+  const uint32_t *words = const_cast<ec_program *>(prog)->device_words(&st);
+  if (!words) return st;
+  ExecArgs a{};
+  set_blocks(a, in, n_in, out, n_out, block_bytes);
+  a.prog = words;
   const int n_cus = device_cus();
   if (n_cus <= 0) return EC_ERR_DEVICE;
   const uint64_t resident = (uint64_t)n_cus * waves_per_simd(prog->slots);  // workgroups of 4 waves
@@ -467,7 +483,24 @@ ec_status ec_device_copy(void *dst, const void *src, size_t bytes, ec_stream str
   if (bytes % 16 || !aligned16(dst) || !aligned16(src)) return EC_ERR_ALIGN;
   const uintptr_t a = (uintptr_t)dst, b = (uintptr_t)src;
   if (a < b + bytes && b < a + bytes) return EC_ERR_ARG;
-  return copy_launch(src, dst, bytes, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
+  const int n_cus = device_cus();
+  if (n_cus <= 0) return EC_ERR_DEVICE;
+  return copy_launch(src, dst, bytes, n_cus, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
+}
+
+ec_status ec_stripe_stream(const uint8_t *const *in, int n_in, uint8_t *const *out, int n_out, size_t block_bytes,
+                           ec_stream stream) {
+  if (!in || !out || n_in < 1 || n_out < 0 || n_in + n_out > kMaxBlocks) return EC_ERR_ARG;
+  ec_status st = check_blocks(in, n_in, out, n_out, block_bytes);
+  if (st != EC_OK) return st;
+  ExecArgs a{};
+  set_blocks(a, in, n_in, out, n_out, block_bytes);
+  const int n_cus = device_cus();
+  if (n_cus <= 0) return EC_ERR_DEVICE;
+  // 8 waves per SIMD (the kernel needs few registers): measured 0.738 of
+  // peak against 0.735 at 3 on the 10 x 64 MiB + 4 x 64 MiB movement
+  const int grid = (int)std::min<uint64_t>(((uint64_t)a.n_tiles + 3) / 4, (uint64_t)n_cus * 8);
+  return stream_launch(a, (uint32_t)n_out, grid, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
 }
 
 ec_status ec_program_upload(ec_program *prog) {

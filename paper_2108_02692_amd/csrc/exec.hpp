@@ -18,9 +18,11 @@ struct ExecArgs {
   uint32_t n_in;             // input blocks
   uint32_t n_tiles;          // ceil(strip_len / kTileBytes)
   uint64_t strip_len;        // bytes per strip (block_bytes / 8), multiple of 16
-  // Work item k runs tile (k & seg_mask) * seg_tiles + (k >> seg_shift):
-  // consecutive waves take tiles in 1 << seg_shift distant segments of the
-  // strips (identity when seg_shift = 0).
+  // Work item k runs tile tile_of(k, ...) (tile_order.hpp): with
+  // seg_shift > 0 the strips are cut into 1 << seg_shift segments of
+  // seg_tiles tiles, and each workgroup's 4 waves take 4 neighbouring tiles
+  // of one segment, consecutive workgroups taking consecutive segments;
+  // the identity when seg_shift = 0.
   uint32_t seg_shift, seg_mask, seg_tiles;
   // Row split: work item k runs part k % n_parts (the program at word
   // part_off[k % n_parts] of prog) on tile k / n_parts; n_parts = 1 and
@@ -62,7 +64,14 @@ int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream);
 // Launch the executor instance for `slots` register slots; 0 on success.
 int exec_launch(int slots, const ExecArgs &a, int grid, hipStream_t stream);
 
-// Device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned).
-int copy_launch(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
+// Device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned) on a
+// device of n_cus compute units.
+int copy_launch(const void *src, void *dst, uint64_t bytes, int n_cus, hipStream_t stream);
+
+// The data movement of one launch of the executor without a program: every
+// tile reads all n_in input strips and writes all n_out output strips (the
+// XOR of its inputs), a.blk holding the input then the output blocks, with
+// the executor's tile order and grid.
+int stream_launch(const ExecArgs &a, uint32_t n_out, int grid, hipStream_t stream);
 
 }  // namespace ec

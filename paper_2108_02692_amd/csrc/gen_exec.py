@@ -183,6 +183,7 @@ HEAD = r'''// exec.hip -- gfx950 executor for push-form XOR programs.
 
 #include "bytecode.hpp"
 #include "exec.hpp"
+#include "tile_order.hpp"
 
 namespace ec {
 
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
       kt = k / n_parts;
       pk = prog + a.part_off[k - kt * n_parts];
     }
-    const uint32_t tile = (kt & a.seg_mask) * a.seg_tiles + (kt >> a.seg_shift);
+    const uint32_t tile = tile_of(kt, a.seg_shift, a.seg_mask, a.seg_tiles);
     const uint64_t toff = (uint64_t)tile * kTileBytes;
     const uint64_t t = tile_table(tab, toff);
     const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
@@ -314,21 +315,6 @@ int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream) {
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
-}
-
-// Plain device copy (16 B per lane, grid-stride): the bandwidth ceiling the
-// executor is compared with, and the calibration kernel for byte counters.
-__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
-                                                   uint64_t n16) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
-}
-
-int copy_launch(const void *src, void *dst, size_t bytes, hipStream_t stream) {
-  const uint64_t n16 = bytes / 16;
-  const int grid = (int)std::min<uint64_t>((n16 + 255) / 256, 256 * 32);
-  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, (const uint4 *)src, (uint4 *)dst, n16);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace ec

@@ -49,9 +49,10 @@ ByteRange g_reads[kMaxRanges], g_writes[kMaxRanges];
 
 // The current device's scratch address and compute units, looked up on the
 // first call on that device (with it current).
-ec_status device_scratch(uint8_t **ptr, int *n_cus) {
+ec_status device_scratch(int *device, uint8_t **ptr, int *n_cus) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return EC_ERR_DEVICE;
+  *device = dev;
   if (!g_scratch[dev]) {
     void *p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EC_ERR_DEVICE;
@@ -74,8 +75,8 @@ extern "C" ec_status ec_batch_run_noalloc(const ec_stripe *stripes, int n_stripe
   if (n_stripes > EC_NOALLOC_MAX_STRIPES) return EC_ERR_CAPACITY;
   std::lock_guard<std::mutex> g(g_mu);
   uint8_t *dev = nullptr;
-  int n_cus = 0;
-  ec_status st = device_scratch(&dev, &n_cus);
+  int device = 0, n_cus = 0;
+  ec_status st = device_scratch(&device, &dev, &n_cus);
   if (st != EC_OK) return st;
   BatchPlan plan;
   st = batch_plan(stripes, n_stripes, tile_bytes, n_cus, &plan);
@@ -83,7 +84,7 @@ extern "C" ec_status ec_batch_run_noalloc(const ec_stripe *stripes, int n_stripe
   if (plan.n_items > kMaxItems) return EC_ERR_CAPACITY;
   StripeDesc *desc = (StripeDesc *)(g_stage + kDescOff);
   uint32_t *items = (uint32_t *)(g_stage + kItemsOff);
-  st = batch_fill(stripes, n_stripes, plan, false, desc, items, g_reads, g_writes);
+  st = batch_fill(stripes, n_stripes, plan, device, false, desc, items, g_reads, g_writes);
   if (st != EC_OK) return st;
   // The descriptors and the items (the counter is reset by the launch's own
   // first kernel, not by a copy or a memset).

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -36,6 +37,10 @@ struct ec_program {
   ec_program_info info{};
   std::mutex mu;
   std::map<int, uint32_t *> dev_words;  // device -> bytecode copy
+  // the same pointers for the first kDevCache device ids, read without the
+  // lock (a batch looks up every stripe's program on every launch)
+  static constexpr int kDevCache = 16;
+  std::atomic<const uint32_t *> dev_cache[kDevCache] = {};
 
   ~ec_program() {
     for (auto &kv : dev_words) {
@@ -58,11 +63,13 @@ struct ec_program {
     stages_built = true;
   }
 
-  // The device copy of the bytecode on the current device, or null if it has
-  // not been uploaded there (allocates nothing).
-  const uint32_t *device_words_present() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  // The device copy of the bytecode on device `dev`, or null if it has not
+  // been uploaded there (allocates nothing).
+  const uint32_t *device_words_present(int dev) {
+    if (dev >= 0 && dev < kDevCache) {
+      const uint32_t *p = dev_cache[dev].load(std::memory_order_acquire);
+      if (p) return p;
+    }
     std::lock_guard<std::mutex> g(mu);
     auto it = dev_words.find(dev);
     return it == dev_words.end() ? nullptr : it->second;
@@ -72,6 +79,13 @@ struct ec_program {
   const uint32_t *device_words(ec_status *st) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { *st = EC_ERR_DEVICE; return nullptr; }
+    return device_words(dev, st);
+  }
+
+  // Device copy of the bytecode for device `dev`, the current device
+  // (uploaded once).
+  const uint32_t *device_words(int dev, ec_status *st) {
+    if (const uint32_t *p = device_words_present(dev)) return p;
     std::lock_guard<std::mutex> g(mu);
     auto it = dev_words.find(dev);
     if (it != dev_words.end()) return it->second;
@@ -84,6 +98,7 @@ struct ec_program {
       return nullptr;
     }
     dev_words[dev] = d;
+    if (dev >= 0 && dev < kDevCache) dev_cache[dev].store(d, std::memory_order_release);
     return d;
   }
 };

@@ -23,6 +23,7 @@
 
 #include "../../include/ec.h"
 #include "arena.hpp"
+#include "batch.hpp"
 #include "exec.hpp"
 #include "program.hpp"
 
@@ -139,15 +140,25 @@ ec_status ec_server_run(ec_server *sv, const ec_request *reqs, int n_reqs, int r
   if (hipGetDevice(&dev) != hipSuccess || dev != sv->device) return EC_ERR_DEVICE;
   const size_t n = (size_t)n_reqs;
   // Check every request up front: a request that could never be admitted
-  // would otherwise stall the loop.
+  // would otherwise stall the loop.  Outputs are placed in the arena, disjoint
+  // from each other by construction, so an input outside the arena is all
+  // that keeps every launch free of overlaps (the launches then skip that
+  // check).
   size_t max_tiles = 1;
   std::vector<const ec_program *> progs;
+  const uintptr_t arena_lo = (uintptr_t)sv->arena, arena_hi = arena_lo + sv->arena_bytes;
   for (size_t i = 0; i < n; ++i) {
     const ec_request &r = reqs[i];
     if (!r.prog || !r.in || !std::isfinite(r.arrival_s) || r.arrival_s < 0) return EC_ERR_ARG;
     if (i > 0 && r.arrival_s < reqs[i - 1].arrival_s) return EC_ERR_ARG;
     if (r.block_bytes == 0 || r.block_bytes % 128 != 0) return EC_ERR_ALIGN;
     if (r.block_bytes / 8 > 0x1FFFFFFFull) return EC_ERR_UNSUPPORTED;
+    for (size_t k = 0; k < n_in_of(r.prog); ++k) {
+      const uintptr_t a = (uintptr_t)r.in[k];
+      if (!a) return EC_ERR_ARG;
+      if (a & 15u) return EC_ERR_ALIGN;
+      if (a < arena_hi && arena_lo < a + r.block_bytes) return EC_ERR_ARG;
+    }
     const size_t out_bytes = n_out_of(r.prog) * r.block_bytes;
     if (out_bytes == 0) return EC_ERR_ARG;
     if ((n_in_of(r.prog) + n_out_of(r.prog)) * r.block_bytes > sv->budget) return EC_ERR_CAPACITY;
@@ -234,7 +245,7 @@ ec_status ec_server_run(ec_server *sv, const ec_request *reqs, int n_reqs, int r
       // one request: a plain launch, without the batch's tables and work counter
       st = launch_one(stripes[0].prog, stripes[0].in, stripes[0].out, stripes[0].block_bytes, s.stream);
     } else {
-      st = ec_batch_set(s.batch, stripes.data(), (int)stripes.size(), 0, (ec_stream)s.stream);
+      st = batch_set(s.batch, stripes.data(), (int)stripes.size(), 0, (ec_stream)s.stream, false);
       if (st == EC_OK) st = ec_batch_enqueue(s.batch, (ec_stream)s.stream);
     }
     if (st != EC_OK) return st;
@@ -254,17 +265,25 @@ ec_status ec_server_run(ec_server *sv, const ec_request *reqs, int n_reqs, int r
       }
     if (!slot || next >= n) continue;
     const double now = realtime ? now_s() - t0 : INFINITY;
-    // Arrived requests spread over the free slots (a request launched alone
-    // on its own stream finishes sooner than in a batch with others), each
-    // launch taking up to max_batch of them.
-    size_t arrived = 0;
+    // The arrived requests' work (bytes read and written; looking at most
+    // max_batch requests per free slot ahead) is spread evenly over the free
+    // slots: a request launched alone on its own stream finishes sooner than
+    // in a batch with others, while a backlog is cut into launches of equal
+    // work, each of up to max_batch requests.
+    size_t arrived = 0, arrived_bytes = 0;
     const size_t cap = n_free * (size_t)sv->max_batch;
-    while (next + arrived < n && reqs[next + arrived].arrival_s <= now && arrived < cap) ++arrived;
-    const size_t take = std::min<size_t>((size_t)sv->max_batch, (arrived + n_free - 1) / n_free);
-    // Arrived requests that fit, up to `take`, all of one slot budget (one
-    // kernel instance per batch).
+    while (next + arrived < n && reqs[next + arrived].arrival_s <= now && arrived < cap) {
+      arrived_bytes += bytes_of(next + arrived);
+      ++arrived;
+    }
+    const size_t share = (arrived_bytes + n_free - 1) / n_free;
+    // Arrived requests that fit, in arrival order, until this launch holds
+    // its share of the work or max_batch requests, all of one slot budget
+    // (one kernel instance per batch).
     int kslots = -1;
-    while (next < n && reqs[next].arrival_s <= now && slot->reqs.size() < take) {
+    size_t launch_bytes = 0;
+    while (next < n && reqs[next].arrival_s <= now && slot->reqs.size() < (size_t)sv->max_batch &&
+           (slot->reqs.empty() || launch_bytes < share)) {
       const ec_request &q = reqs[next];
       if (kslots >= 0 && q.prog->slots != kslots) break;
       if (used + bytes_of(next) > sv->budget) break;
@@ -275,6 +294,7 @@ ec_status ec_server_run(ec_server *sv, const ec_request *reqs, int n_reqs, int r
       out_len[next] = got;
       used += bytes_of(next);
       kslots = q.prog->slots;
+      launch_bytes += bytes_of(next);
       slot->reqs.push_back((int)next);
       ++next;
     }

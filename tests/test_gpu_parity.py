@@ -401,3 +401,26 @@ def test_random_cases_match_oracle():
         else:
             assert_blocks_equal(run_encode(prog, data, S), blocks[n:], what)
         done += 1
+
+
+@pytest.mark.parametrize("S", [128, 8192 + 128, 1 << 20, 32 << 20])
+def test_stripe_stream_reference_kernel(S):
+    """ec_stripe_stream (the coding launch's data movement without a program,
+    a measurement reference): every output strip is the XOR of all input
+    strips at the same offset (numpy), on ragged sizes and on 4 MiB strips
+    (the segment tile order); ec_device_copy copies exactly."""
+    n_in, n_out = 10, 4
+    data = W.host_blocks(n_in, S, seed=S % 997)
+    want = np.bitwise_xor.reduce(np.stack([b.reshape(8, S // 8) for b in data]).reshape(-1, S // 8), axis=0)
+    out = W.empty_blocks(n_out, S, fill=0xA5)
+    E.ec_stripe_stream(W.to_device(data), out, S)
+    torch.cuda.synchronize()
+    for j, o in enumerate(out):
+        got = o.cpu().numpy().reshape(8, S // 8)
+        for r in range(8):
+            assert np.array_equal(got[r], want), "output %d strip %d" % (j, r)
+    src = torch.from_numpy(data[0]).cuda()
+    dst = torch.full((S + 64,), 0x5A, dtype=torch.uint8, device="cuda")
+    E.ec_device_copy(dst, src, S)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:S], src) and bool((dst[S:] == 0x5A).all())
