@@ -37,13 +37,15 @@ def parse():
     # untimed launches of the timed kernel before each timed run (after the
     # copies of prewarm())
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--prewarm-ms", type=float, default=50.0,
+                    help="ms of device copies before each timed run's warm-up launches (0 = none; counter runs)")
     ap.add_argument("--block-mib", type=int, default=64)
     ap.add_argument("--slots", type=int, default=0, help="slot budget of the compressed program (0 = default)")
     ap.add_argument("--plain-slots", type=int, default=0, help="slot budget of the plain program (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
     ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve",
-                                       "decode_all", "codecs", "small", "schedulers"],
+                                       "decode_all", "codecs", "small", "schedulers", "batched_programs"],
                     default="all",
                     help="time one kernel only (for profiler runs)")
     ap.add_argument("--calib", action="store_true",
@@ -93,12 +95,12 @@ def prewarm(stream, ms=PREWARM_MS):
     return ms
 
 
-def time_launches(fn, steps, warmup, stream, prewarm_ms=PREWARM_MS):
+def time_launches(fn, steps, warmup, stream, prewarm_ms=None):
     """Average ms per launch over `steps` back-to-back launches, bracketed by
     HIP events on the stream the kernels run on, after `prewarm_ms` of
     device copies and `warmup` untimed launches."""
     import torch
-    prewarm(stream, prewarm_ms)
+    prewarm(stream, PREWARM_MS if prewarm_ms is None else prewarm_ms)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -161,6 +163,8 @@ def measured_traffic(prog):
 
 def main():
     args = parse()
+    global PREWARM_MS
+    PREWARM_MS = args.prewarm_ms
     if args.gpus != 1:
         print("bench.py: the executor runs on one GPU; --gpus %d is not supported (stripes would be "
               "sharded across GPUs by the caller, one process per GPU)" % args.gpus, file=sys.stderr)
@@ -176,6 +180,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.only == "batched":
         print(json.dumps({"batched": bench_batched(args, stream)}), flush=True)
+        return
+    if args.only == "batched_programs":
+        print(json.dumps({"batched_programs": bench_batched_programs(args, stream)}), flush=True)
         return
     if args.only == "decode_all":
         print(json.dumps({"decode_all": bench_decode_all(args, stream)}), flush=True)
@@ -537,6 +544,56 @@ def bench_batched(args, stream):
     batch.free()
     del pool, out_buf, inputs, outputs
     return res
+
+
+def bench_batched_programs(args, stream):
+    """The batched workload's block sizes in three batches, to separate the
+    cost of many programs in one launch: the 8192-stripe mix itself (1713
+    programs), RS(10,4) encodes only (one program) and RS(10,4) decodes of
+    uniformly drawn erasure sets (up to 1470 programs), each of the same
+    8192 block sizes with inputs drawn from the same pool.  Each batch: the
+    time per launch and its algorithmic bytes (a byte-counter run of this
+    command gives the fetched bytes per dispatch, in this order, 1 + steps
+    dispatches each)."""
+    import itertools
+    import numpy as np
+    import torch
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import autotune, batching
+    specs, pool, inputs, outputs, _ = batching.mixed_workload(args.batch_stripes, hi=args.batch_max_mib << 20)
+    # outputs of the RS(10,4) batches (at most 4 blocks per stripe)
+    out_buf = torch.empty(sum(4 * s.block_bytes for s in specs), dtype=torch.uint8, device="cuda")
+    cache = batching.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=44)
+    rng = np.random.default_rng(9)
+    pats = [c for r in range(1, 5) for c in itertools.combinations(range(14), r)]
+
+    def rs10_4(decode):
+        sp, ins, outs, off = [], [], [], 0
+        for s0 in specs:
+            bb = s0.block_bytes
+            s = batching.StripeSpec(10, 4, bb, pats[int(rng.integers(len(pats)))] if decode else ())
+            sp.append(s)
+            top = (pool.numel() - bb) // 4096
+            ins.append([pool[o:o + bb] for o in (rng.integers(0, top, 10) * 4096).tolist()])
+            outs.append([out_buf[off + j * bb: off + (j + 1) * bb] for j in range(s.n_out)])
+            off += s.n_out * bb
+        assert off <= out_buf.numel()
+        return sp, ins, outs
+
+    rows = []
+    for name, (sp, ins, outs) in (("mix", (specs, inputs, outputs)), ("rs10_4_encode", rs10_4(False)),
+                                  ("rs10_4_decodes", rs10_4(True))):
+        cache.warm({(s.n, s.p, s.erased) for s in sp})
+        batch = batching.build_batch(sp, cache, ins, outs, stream=stream)
+        ms = autotune.time_batch(batch, stream, steps=max(3, args.steps // 2), warmup=1)
+        rd = sum(s.n_in * s.block_bytes for s in sp)
+        wr = sum(s.n_out * s.block_bytes for s in sp)
+        rows.append({"batch": name, "stripes": len(sp), "programs": len({(s.n, s.p, s.erased) for s in sp}),
+                     "work_items": batch.n_items, "read_bytes": rd, "write_bytes": wr, "ms": ms,
+                     "hbm_frac": (rd + wr) / ms / 1e6 / HBM_PEAK_GBS, "launches": 1 + max(3, args.steps // 2)})
+        log("%s: %.3f ms, %.3f of peak" % (name, ms, rows[-1]["hbm_frac"]))
+        batch.free()
+    return rows
 
 
 def bench_decode_all(args, stream):

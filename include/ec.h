@@ -92,10 +92,11 @@ enum {
 typedef struct {
   uint32_t level;        /* EC_LEVEL_*; default EC_LEVEL_CO_FU_SCHED */
   uint32_t slot_budget;  /* register slots per lane (16 B each); supported: 24, 32, 36, 38, 40,
-                            44, 48 (the executor runs 4 waves per SIMD up to 24 slots, 3 up to
-                            38, else 2); 0 = default: the first of 24, 32, 38, 44, 48 that holds
-                            every output row in one pass over the inputs with a ring of at
-                            least 3 strip loads (48 if none does) */
+                            44, 48, 56, 60 (the executor runs 4 waves per SIMD up to 24 slots, 3
+                            up to 38, else 2); 0 = default: the first of 24, 32, 38, 44, 48 that
+                            holds every output row in one pass over the inputs with a ring of
+                            at least 3 strip loads, else the first of 56, 60 that does, else 48
+                            (several passes) */
   uint32_t compress;     /* EC_COMPRESS_*; default XorRePair */
   uint32_t block_strips; /* width in strips of the column blocks compressed separately
                             (levels >= CO); 0 = 8, one data block; 8*n = the whole matrix */
@@ -116,7 +117,13 @@ typedef struct {
  *  - row parts: up to 32, each one bit row (beyond 4 output blocks, runs
  *    of floor or ceil(8 n_out / 32) consecutive rows);
  *  - pair parts: up to 16, each two consecutive bit rows (beyond 4 output
- *    blocks, runs of floor or ceil(8 n_out / 32) pairs).
+ *    blocks, runs of floor or ceil(8 n_out / 32) pairs);
+ *  - pass parts (only for a program whose rows need several passes over the
+ *    inputs): the fewest groups of whole output blocks that each fit one
+ *    pass, scheduled from the program itself.  The parts of a tile run on
+ *    neighbouring waves of one workgroup at the same time, so each input
+ *    strip-tile comes from HBM once and from the caches for the other parts
+ *    (a single wave reads it from HBM again on every pass).
  * A launch over a stripe with few tiles then runs one wave per (tile, part)
  * instead of one per tile, which gives short stripes more waves and each
  * wave a shorter chain of records and a deeper load ring, at the cost of
@@ -127,11 +134,13 @@ enum {
   EC_SPLIT_AUTO = 0,   /* the finest set that fits, none if no set does (default): row parts,
                           then pair parts, while one wave per (tile, part) leaves at most two
                           waves per SIMD; block parts while those waves fit in the waves the
-                          chip keeps resident for the program's slot budget */
+                          chip keeps resident for the program's slot budget; else pass parts,
+                          when the program has them */
   EC_SPLIT_NEVER = 1,  /* one wave per tile; no parts are built */
   EC_SPLIT_ALWAYS = 2, /* block parts on every launch when the program has them */
   EC_SPLIT_ROWS = 3,   /* row parts on every launch when the program has them */
-  EC_SPLIT_PAIRS = 4   /* pair parts on every launch when the program has them */
+  EC_SPLIT_PAIRS = 4,  /* pair parts on every launch when the program has them */
+  EC_SPLIT_PASSES = 5  /* pass parts on every launch when the program has them */
 };
 
 typedef struct {
@@ -155,6 +164,7 @@ typedef struct {
   uint32_t n_parts;     /* block parts for the row split (0: none, e.g. one output block) */
   uint32_t n_row_parts; /* row parts for the row split (0: none) */
   uint32_t n_pair_parts; /* pair parts for the row split (0: none) */
+  uint32_t n_pass_parts; /* pass parts (0: none; the program needs one pass) */
   uint32_t scheduler;   /* EC_SCHED_* the strip order was made with */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
@@ -281,7 +291,8 @@ ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, si
 /* The bytecode of part `part` of a program: block part `part` for
  * 0 <= part < info.n_parts, then row part `part - n_parts` for
  * part < n_parts + n_row_parts, then pair part `part - n_parts -
- * n_row_parts` up to n_parts + n_row_parts + n_pair_parts (host copy; same record format as
+ * n_row_parts` up to n_parts + n_row_parts + n_pair_parts, then the pass
+ * parts up to that plus n_pass_parts (host copy; same record format as
  * ec_program_bytecode, storing only the part's output rows).  EC_ERR_ARG for
  * a part that does not exist. */
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words);

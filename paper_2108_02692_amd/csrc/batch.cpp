@@ -95,6 +95,9 @@ const std::vector<uint32_t> *split_offsets(const ec_program *prog, const BatchPl
     return prog->pair_parts.empty() ? nullptr : &prog->pair_part_off;
   if (prog->split == EC_SPLIT_ALWAYS || (prog->split == EC_SPLIT_AUTO && plan.blocks_fit))
     return prog->parts.empty() ? nullptr : &prog->part_off;
+  // a program that needs several passes over its inputs runs its pass parts
+  if (prog->split == EC_SPLIT_PASSES || prog->split == EC_SPLIT_AUTO)
+    return prog->pass_parts.empty() ? nullptr : &prog->pass_part_off;
   return nullptr;
 }
 

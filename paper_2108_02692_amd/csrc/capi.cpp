@@ -21,7 +21,7 @@ using namespace ec;
 
 namespace {
 
-constexpr uint32_t kSlotBudgets[] = {24, 32, 36, 38, 40, 44, 48};  // executor kernels built
+constexpr uint32_t kSlotBudgets[] = {24, 32, 36, 38, 40, 44, 48, 56, 60};  // executor kernels built
 
 // Record overhead of the executor in slot-XOR units: the unfolding trade-off
 // of a temporary (one record against the XORs it saves).
@@ -135,20 +135,25 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   const uint64_t waves = 4 * resident;
   const std::vector<uint32_t> *off = nullptr;
   const uint64_t nb = prog->parts.size(), nr = prog->row_parts.size(), np = prog->pair_parts.size();
+  const uint64_t ns = prog->pass_parts.size();
   if (prog->split == EC_SPLIT_ROWS) {
     if (nr) off = &prog->row_part_off;
   } else if (prog->split == EC_SPLIT_PAIRS) {
     if (np) off = &prog->pair_part_off;
   } else if (prog->split == EC_SPLIT_ALWAYS) {
     if (nb) off = &prog->part_off;
+  } else if (prog->split == EC_SPLIT_PASSES) {
+    if (ns) off = &prog->pass_part_off;
   } else if (prog->split == EC_SPLIT_AUTO) {
     // The finest set that fits: row or pair parts while there are at most
     // two waves per SIMD (their chains run side by side), block parts while
-    // all their waves are resident.
+    // all their waves are resident; else pass parts when the program needs
+    // several passes over the inputs.
     const uint64_t fine = 2ull * 4 * (uint64_t)n_cus;
     if (nr && a.n_tiles * nr <= fine) off = &prog->row_part_off;
     else if (np && a.n_tiles * np <= fine) off = &prog->pair_part_off;
     else if (nb && a.n_tiles * nb <= waves) off = &prog->part_off;
+    else if (ns) off = &prog->pass_part_off;
   }
   if (off) {
     a.n_parts = (uint32_t)off->size();
@@ -205,7 +210,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (o.scheduler > EC_SCHED_GREEDY) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
-  if (o.split > EC_SPLIT_PAIRS) return EC_ERR_UNSUPPORTED;
+  if (o.split > EC_SPLIT_PASSES) return EC_ERR_UNSUPPORTED;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -268,13 +273,31 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     // The budgets that set the executor's occupancy (4, 3 and 2 waves per
     // SIMD for 24, 38 and 48 slots; 32 and 44 in between), smallest first:
     // the first that holds every row in one pass over the inputs with a ring
-    // of at least 3 loads.
+    // of at least 3 loads.  Past 48, only to save a pass: 56 and 60 slots
+    // still run 2 waves per SIMD (up to 256 VGPRs), and rows that need a
+    // second pass would read every input again.
     int rc = -1;
     for (uint32_t k : {24u, 32u, 38u, 44u, 48u}) {
       po.slots = (int)k;
       order(dag, po.slots);
       rc = push_schedule(dag, n_in, po, prog->code);
       if (rc == 0 && ((prog->code.passes == 1 && prog->code.ring >= 3) || k == 48)) break;
+    }
+    if (rc != 0 || prog->code.passes > 1) {
+      PushOpts wide = po;
+      for (int k : {56, 60}) {
+        wide.slots = k;
+        PushDag trial = dag;
+        order(trial, k);
+        PushCode code;
+        if (push_schedule(trial, n_in, wide, code) == 0 && code.passes == 1 && code.ring >= 3) {
+          dag = trial;
+          prog->code = code;
+          po = wide;
+          return 0;
+        }
+      }
+      po.slots = 48;  // (the order for 48 stays in dag: order() was last applied with 48)
     }
     return rc;
   };
@@ -366,6 +389,38 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     if (n_rows > 1 && !build_parts(1, kMaxRowParts, prog->row_parts)) return EC_ERR_UNSUPPORTED;
     if (n_rows > 2 && !build_parts(2, kMaxRowParts / 2, prog->pair_parts)) return EC_ERR_UNSUPPORTED;
   }
+  // Pass parts: when the rows need several passes over the inputs, the
+  // fewest groups of whole output blocks that each fit one pass, scheduled
+  // from the program itself (its level and order).  The parts of one tile
+  // run on neighbouring waves of one workgroup at the same time, so an
+  // input strip-tile is fetched from HBM once and found in the caches by the
+  // other parts, where a single wave would read it again from HBM on every
+  // pass (the register file holds one level of the cache hierarchy, the
+  // caches the next).
+  prog->pass_parts.clear();
+  prog->pass_part_off.clear();
+  if (o.split != EC_SPLIT_NEVER && prog->code.passes > 1) {
+    for (int groups = prog->code.passes; groups <= std::min(n_out, kMaxParts); ++groups) {
+      std::vector<PushCode> set;
+      bool fits = true;
+      for (int g = 0; g < groups && fits; ++g) {
+        PushOpts pp = po;
+        pp.row_lo = 8 * (g * n_out / groups);
+        pp.row_hi = 8 * ((g + 1) * n_out / groups);
+        PushCode part;
+        fits = push_schedule(dag, n_in, pp, part) == 0 && part.passes == 1;
+        if (fits) {
+          if (!simulate_code(part.words, prog->slots, n_in, n_out, brows, pp.row_lo, pp.row_hi))
+            return EC_ERR_UNSUPPORTED;
+          set.push_back(std::move(part));
+        }
+      }
+      if (fits) {
+        prog->pass_parts = std::move(set);
+        break;
+      }
+    }
+  }
   for (const PushCode &part : prog->parts) {
     prog->part_off.push_back((uint32_t)prog->image.size());
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
@@ -376,6 +431,10 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   }
   for (const PushCode &part : prog->pair_parts) {
     prog->pair_part_off.push_back((uint32_t)prog->image.size());
+    prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
+  }
+  for (const PushCode &part : prog->pass_parts) {
+    prog->pass_part_off.push_back((uint32_t)prog->image.size());
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
@@ -402,6 +461,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_parts = (uint32_t)prog->parts.size();
   info.n_row_parts = (uint32_t)prog->row_parts.size();
   info.n_pair_parts = (uint32_t)prog->pair_parts.size();
+  info.n_pass_parts = (uint32_t)prog->pass_parts.size();
   info.scheduler = o.scheduler;
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
@@ -513,9 +573,12 @@ ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint3
   if (!prog || !words || !n_words || part < 0) return EC_ERR_ARG;
   const int nb = (int)prog->parts.size();
   const int nr = (int)prog->row_parts.size();
-  if (part >= nb + nr + (int)prog->pair_parts.size()) return EC_ERR_ARG;
-  const PushCode &c = part < nb ? prog->parts[part]
-                      : part < nb + nr ? prog->row_parts[part - nb] : prog->pair_parts[part - nb - nr];
+  const int np = (int)prog->pair_parts.size();
+  if (part >= nb + nr + np + (int)prog->pass_parts.size()) return EC_ERR_ARG;
+  const PushCode &c = part < nb        ? prog->parts[part]
+                      : part < nb + nr ? prog->row_parts[part - nb]
+                      : part < nb + nr + np ? prog->pair_parts[part - nb - nr]
+                                            : prog->pass_parts[part - nb - nr - np];
   *words = c.words.data();
   *n_words = c.words.size();
   return EC_OK;

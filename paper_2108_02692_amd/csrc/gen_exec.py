@@ -6,7 +6,7 @@ The record format it interprets is described in bytecode.hpp.
 """
 import os
 
-SLOT_BUDGETS = (24, 32, 36, 38, 40, 44, 48)
+SLOT_BUDGETS = (24, 32, 36, 38, 40, 44, 48, 56, 60)
 WA, WB = 36, 52          # the two 16-SGPR record windows
 MAX_OPS = 14
 STEP_BYTES = 20

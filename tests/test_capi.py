@@ -37,7 +37,7 @@ def test_status_strings():
         assert E.ec_status_str(s) and E.ec_status_str(s) != "unknown status"
 
 
-SLOT_BUDGETS = [24, 32, 36, 38, 40, 44, 48]
+SLOT_BUDGETS = [24, 32, 36, 38, 40, 44, 48, 56, 60]
 OBJDUMP = os.path.join(os.path.dirname(_build.HIPCC), "..", "llvm", "bin", "llvm-objdump")
 
 

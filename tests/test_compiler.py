@@ -168,7 +168,7 @@ def test_greedy_export_errors():
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
-@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48, 56, 60])
 def test_bytecode_simulates_to_bitmatrix(level, K):
     n, p = 10, 4
     gen = E.ec_matrix_cauchy(n, p)
@@ -214,7 +214,7 @@ def greedy_first_reads(stmts, outs, capacity, width):
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
-@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48, 56, 60])
 def test_greedy_scheduler_programs(level, K):
     """EC_SCHED_GREEDY at every level and slot budget: the records compute
     the bitmatrix rows (independent simulator), and a single-pass program
@@ -326,7 +326,7 @@ def test_compile_errors():
         E.ec_compile_slp(10, 4, gen, block_strips=81)
     assert e.value.name == "EC_ERR_ARG"
     with pytest.raises(E.EcError) as e:
-        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_PAIRS + 1)
+        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_PASSES + 1)
     assert e.value.name == "EC_ERR_UNSUPPORTED"
     with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
@@ -339,26 +339,30 @@ def test_compile_errors():
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
 def test_row_split_parts_cover_the_rows(n, p, er, level):
     """Every row-split part, run by the independent simulator, stores only its
-    own output rows; each set of parts (blocks, single rows, pairs of rows)
-    stores every output strip with the bitmatrix row's value, exactly once."""
+    own output rows; each set of parts (blocks, single rows, pairs of rows,
+    passes) stores every output strip with the bitmatrix row's value, exactly
+    once."""
     gen = E.ec_matrix_cauchy(n, p)
     rows = oracle_rows(gen, n, p, er)
     prog = E.ec_compile_slp(n, p, gen, er, level=level)
     n_out = len(prog.out_blocks)
     nb, nr, npair = prog.info["n_parts"], prog.info["n_row_parts"], prog.info["n_pair_parts"]
+    npass = prog.info["n_pass_parts"]
     assert nb == (min(n_out, 8) if n_out > 1 else 0) or nb == 0
     assert nr == min(8 * n_out, 32) or nr == 0
     assert npair == min(4 * n_out, 16) or npair == 0
+    assert (npass >= prog.info["passes"]) if prog.info["passes"] > 1 else npass == 0
 
     def sizes(unit, groups):  # rows per part of a set of runs of `unit` rows
         units = 8 * n_out // unit
         return {unit * (units // groups), unit * -(-units // groups)} - {0}
-    for lo, hi, kind in ((0, nb, "block"), (nb, nb + nr, "row"), (nb + nr, nb + nr + npair, "pair")):
+    n4 = nb + nr + npair
+    for lo, hi, kind in ((0, nb, "block"), (nb, nb + nr, "row"), (nb + nr, n4, "pair"), (n4, n4 + npass, "pass")):
         got = {}
         for q in range(lo, hi):
             part = simulate(prog.part_bytecode(q), prog.info["slots"], len(prog.in_blocks), n_out)
             assert part and not set(part) & set(got)
-            if kind == "block":
+            if kind in ("block", "pass"):
                 assert all(8 * (o // 8) + j in part for o in part for j in range(8))
             else:  # a run of rows right after the previous part's, of even size
                 assert sorted(part) == list(range(len(got), len(got) + len(part)))
@@ -368,7 +372,8 @@ def test_row_split_parts_cover_the_rows(n, p, er, level):
             assert [got[o] for o in range(len(rows))] == rows
     info = E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_NEVER).info
     assert info["n_parts"] == 0 and info["n_row_parts"] == 0 and info["n_pair_parts"] == 0
+    assert info["n_pass_parts"] == 0
     with pytest.raises(E.EcError):
-        prog.part_bytecode(nb + nr + npair)
+        prog.part_bytecode(n4 + npass)
     with pytest.raises(E.EcError):
         prog.part_bytecode(-1)

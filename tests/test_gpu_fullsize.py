@@ -130,6 +130,41 @@ def test_segment_order_single_launch_and_batch():
             first_diff(rec[j].cpu().numpy(), want_dec[er.index(e)], "%s decode block %d" % (mode, e))
 
 
+@pytest.mark.parametrize("n,p,er,K", [(12, 6, (), 48), (12, 6, (0, 3, 7, 12, 16, 17), 48), (4, 12, (), 0),
+                                      (12, 6, (), 0), (12, 6, (0, 3, 7, 12, 16, 17), 0), (10, 6, (), 0)])
+def test_wide_codecs_64mib_every_byte(n, p, er, K):
+    """Codecs with more rows than 48 slots hold: by default a 56- or
+    60-slot program in one pass where the rows fit, else (and with 48 slots
+    forced) several passes run as pass parts, the library's default for such
+    stripes.  64 MiB blocks, every byte of every output against the oracle."""
+    S = 64 << 20
+    G = oracle.cauchy(n, p)
+    data = W.device_blocks(n, S, seed=n + 7 * p)
+    host = [d.cpu().numpy() for d in data]
+    par = oracle.encode(G, n, p, host, threads=THREADS)
+    prog = E.ec_compile_slp(n, p, gen_rows(n, p), list(er), slot_budget=K)
+    if K == 48 or (n, p) == (4, 12):
+        assert prog.info["passes"] > 1 and prog.info["n_pass_parts"] >= prog.info["passes"]
+    else:
+        assert prog.info["passes"] == 1 and prog.info["slots"] in (56, 60)
+    if er:
+        blocks = host + par
+        dev = list(data) + W.to_device(par)
+        out = W.empty_blocks(len(er), S, fill=0xA5)
+        E.ec_decode(prog, [dev[i] for i in prog.in_blocks], out, S)
+        torch.cuda.synchronize()
+        want = [blocks[e] for e in prog.out_blocks]
+    else:
+        out = W.empty_blocks(p, S, fill=0xA5)
+        E.ec_encode(prog, data, out, S)
+        torch.cuda.synchronize()
+        want = par
+    for j, w in enumerate(want):
+        first_diff(out[j].cpu().numpy(), w, "RS(%d,%d) %s K %d, output %d" % (n, p, er, K, j))
+    del data, out
+    torch.cuda.empty_cache()
+
+
 def _subset(specs, count=24, seed=8):
     """The largest stripe of each (codec, encode/decode), then seeded others."""
     pick = {}

@@ -74,7 +74,7 @@ def compile_many(n, p, gen, patterns, **kw):
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
-@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48, 56, 60])
 def test_encode_rs10_4_1mib(level, K):
     """RS(10,4) encode, 10 x 1 MiB blocks of seeded random bytes."""
     n, p, S = 10, 4, 1 << 20
@@ -84,7 +84,7 @@ def test_encode_rs10_4_1mib(level, K):
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED])
-@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48])
+@pytest.mark.parametrize("K", [24, 32, 36, 38, 40, 44, 48, 56, 60])
 def test_greedy_scheduler_rs10_4(level, K):
     """Programs whose strip order comes from the bottom-up greedy heuristic
     (EC_SCHED_GREEDY): RS(10,4) encode and the decode of {2, 4, 5, 6} on
@@ -351,18 +351,19 @@ def test_launch_argument_errors():
 
 
 @pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, ()), (14, 4, (0, 13)), (2, 1, ()),
-                                    (4, 12, ()), (2, 10, ()), (4, 12, tuple(range(1, 12)))])
+                                    (4, 12, ()), (2, 10, ()), (4, 12, tuple(range(1, 12))), (12, 6, ()),
+                                    (8, 8, (0, 3, 9, 10, 11, 12, 13, 15))])
 def test_row_split_matches_oracle(n, p, er):
-    """Short stripes run one wave per (tile, part): row, pair and block parts
-    forced, the split off and left to the library, on ragged and small block
-    sizes, equal the oracle."""
+    """Short stripes run one wave per (tile, part): row, pair, block and
+    pass parts forced, the split off and left to the library, on ragged and
+    small block sizes, equal the oracle."""
     gen = oracle_gen(n, p)
     G = np.array(gen, dtype=np.uint8)
     for S in (4096 + 128, 1 << 20, 3 * (1 << 20) + 384):
         data = W.host_blocks(n, S, seed=S % 1000 + n)
         blocks = data + oracle.encode(G, n, p, data)
         want = [blocks[e] for e in er] if er else blocks[n:]
-        for split in (E.SPLIT_ROWS, E.SPLIT_PAIRS, E.SPLIT_ALWAYS, E.SPLIT_NEVER, E.SPLIT_AUTO):
+        for split in (E.SPLIT_ROWS, E.SPLIT_PAIRS, E.SPLIT_ALWAYS, E.SPLIT_PASSES, E.SPLIT_NEVER, E.SPLIT_AUTO):
             prog = E.ec_compile_slp(n, p, gen, list(er), split=split)
             got = run_decode(prog, blocks, S) if er else run_encode(prog, data, S)
             assert_blocks_equal(got, want, "RS(%d,%d) %s S=%d split %d" % (n, p, er, S, split))
@@ -373,7 +374,7 @@ def test_random_cases_match_oracle():
     blocks), erasure set, level, slot budget, split policy and block size
     (any multiple of 128 B up to 384 KiB), each compared with the oracle."""
     rng = random.Random(2024)
-    budgets = (0, 24, 32, 36, 38, 40, 44, 48)
+    budgets = (0, 24, 32, 36, 38, 40, 44, 48, 56, 60)
     levels = (E.LEVEL_PLAIN, E.LEVEL_CO, E.LEVEL_CO_FU, E.LEVEL_CO_FU_SCHED)
     splits = (E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS, E.SPLIT_ROWS, E.SPLIT_PAIRS)
     done = 0
