@@ -246,17 +246,22 @@ def cancel(ops):
 
 # ------------------------------------------------------------ DFS schedule
 def dfs_order(stmts, outputs, is_const):
-    """Post-order of the computation graph (Sec. 6.4, 6.6): roots are the
-    statements no other statement uses, visited in term order; children are
-    visited in term order (variables before constants).  Returns the
-    statements in the new order."""
+    """Post-order of the computation graph (Sec. 6.4, 6.6): the goals (the
+    returned variables) are the roots, visited in the order they are
+    returned, then any other statement no statement uses, by variable;
+    children are visited in term order (variables before constants).
+    Returns the statements in the new order."""
     by_var = {v: ops for v, ops in stmts}
     used = set()
     for _, ops in stmts:
         for o in ops:
             if o in by_var:
                 used.add(o)
-    roots = sorted(v for v, _ in stmts if v not in used)
+    roots = []
+    for o in outputs:
+        if o in by_var and o not in roots:
+            roots.append(o)
+    roots += sorted(v for v, _ in stmts if v not in used and v not in roots)
     # goals not reachable as roots are still computed (they are used)
     seen = set()
     order = []

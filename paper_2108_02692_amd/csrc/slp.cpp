@@ -213,9 +213,14 @@ Slp dfs_schedule(const Slp &in) {
   for (const Stmt &s : in.stmts)
     for (int o : s.ops)
       if (by_var.count(o)) used.insert(o);
+  // roots: the returned variables in the order they are returned, then the
+  // other statements no statement uses, by variable (map order)
   std::vector<int> roots;
+  std::set<int> is_root;
+  for (int o : in.outputs)
+    if (by_var.count(o) && is_root.insert(o).second) roots.push_back(o);
   for (const auto &kv : by_var)
-    if (!used.count(kv.first)) roots.push_back(kv.first);  // map order = var order
+    if (!used.count(kv.first) && is_root.insert(kv.first).second) roots.push_back(kv.first);
   std::set<int> seen;
   Slp out;
   out.n_const = in.n_const;

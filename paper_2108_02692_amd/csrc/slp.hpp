@@ -62,7 +62,8 @@ Slp xor_repair(const std::vector<Bits> &rows, int n_const, bool rebuild);
 // XOR fusion (Sec. 5.2).
 Slp fuse(const Slp &in);
 
-// DFS post-order over the computation graph (Sec. 6.6).
+// DFS post-order over the computation graph (Sec. 6.6), from the returned
+// variables in their order, then from any other statement no statement uses.
 Slp dfs_schedule(const Slp &in);
 
 // Bottom-up greedy heuristic (Sec. 6.6) for an LRU cache of `capacity`
