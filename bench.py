@@ -547,30 +547,34 @@ def bench_batched(args, stream):
 
 
 def bench_batched_programs(args, stream):
-    """The batched workload's block sizes in three batches, to separate the
-    cost of many programs in one launch: the 8192-stripe mix itself (1713
-    programs), RS(10,4) encodes only (one program) and RS(10,4) decodes of
-    uniformly drawn erasure sets (up to 1470 programs), each of the same
-    8192 block sizes with inputs drawn from the same pool.  Each batch: the
-    time per launch and its algorithmic bytes (a byte-counter run of this
-    command gives the fetched bytes per dispatch, in this order, 1 + steps
-    dispatches each)."""
+    """The batched workload's block sizes in four batches, to separate the
+    cost of many programs in one launch and of strips that start off a
+    128-byte line: the 8192-stripe mix itself (1713 programs), RS(10,4)
+    encodes only (one program), RS(10,4) decodes of uniformly drawn erasure
+    sets (up to 1470 programs), each of the same 8192 block sizes (multiples
+    of 512 B, so a strip may start 64 B into a line), and the RS(10,4)
+    encodes with the sizes rounded up to 1 KiB (every strip on a line
+    boundary); inputs drawn from the same pool.  Each batch: the time per
+    launch and its algorithmic bytes (a byte-counter run of this command
+    gives the fetched bytes per dispatch, in this order, 1 + max(3, steps /
+    2) dispatches each)."""
     import itertools
     import numpy as np
     import torch
     import paper_2108_02692_amd as E
     from paper_2108_02692_amd import autotune, batching
     specs, pool, inputs, outputs, _ = batching.mixed_workload(args.batch_stripes, hi=args.batch_max_mib << 20)
-    # outputs of the RS(10,4) batches (at most 4 blocks per stripe)
-    out_buf = torch.empty(sum(4 * s.block_bytes for s in specs), dtype=torch.uint8, device="cuda")
+    # outputs of the RS(10,4) batches (at most 4 blocks per stripe, blocks
+    # rounded up to 1 KiB at most)
+    out_buf = torch.empty(sum(4 * (s.block_bytes + 512) for s in specs), dtype=torch.uint8, device="cuda")
     cache = batching.ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=44)
     rng = np.random.default_rng(9)
     pats = [c for r in range(1, 5) for c in itertools.combinations(range(14), r)]
 
-    def rs10_4(decode):
+    def rs10_4(decode, align=512):
         sp, ins, outs, off = [], [], [], 0
         for s0 in specs:
-            bb = s0.block_bytes
+            bb = -(-s0.block_bytes // align) * align
             s = batching.StripeSpec(10, 4, bb, pats[int(rng.integers(len(pats)))] if decode else ())
             sp.append(s)
             top = (pool.numel() - bb) // 4096
@@ -582,7 +586,7 @@ def bench_batched_programs(args, stream):
 
     rows = []
     for name, (sp, ins, outs) in (("mix", (specs, inputs, outputs)), ("rs10_4_encode", rs10_4(False)),
-                                  ("rs10_4_decodes", rs10_4(True))):
+                                  ("rs10_4_decodes", rs10_4(True)), ("rs10_4_encode_1KiB", rs10_4(False, 1024))):
         cache.warm({(s.n, s.p, s.erased) for s in sp})
         batch = batching.build_batch(sp, cache, ins, outs, stream=stream)
         ms = autotune.time_batch(batch, stream, steps=max(3, args.steps // 2), warmup=1)
