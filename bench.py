@@ -495,8 +495,13 @@ def bench_serving(args, batched_GB_s=None):
     then a sweep of arrival rates (about 40,000 requests each) up to the
     drain, where every request is present at once."""
     import numpy as np
+    import paper_2108_02692_amd as E
     from paper_2108_02692_amd import serve
+    c0, _, _ = E.ec_program_pool_stats()
+    t0 = time.perf_counter()
     server = serve.Server()
+    setup_s = time.perf_counter() - t0
+    c1, images, pool_bytes = E.ec_program_pool_stats()
     runs = [serve.run(duration_s=args.serve_seconds, seed=7, server=server) for _ in range(max(1, args.serve_runs))]
     res = dict(runs[0])
     for k in ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s", "requests_per_launch"):
@@ -511,6 +516,11 @@ def bench_serving(args, batched_GB_s=None):
         log("serving at %.0f req/s: %.1f GB/s, p50 %.3f ms, p99 %.3f ms, %.1f requests per launch"
             % (rate, r["GB_s"], r["p50_ms"], r["p99_ms"], r["requests_per_launch"]))
     res["sweep"] = sweep
+    # compiling and uploading the server's programs (every erasure pattern
+    # of its codecs): the device allocations the upload made, the distinct
+    # records and their bytes
+    res["setup"] = {"seconds": setup_s, "programs": len(server.cache), "pool_allocations": c1 - c0,
+                    "pool_records": images, "pool_bytes": pool_bytes}
     if batched_GB_s:
         res["drain_vs_batched"] = res["drain_GB_s"] / batched_GB_s
     return res

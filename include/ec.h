@@ -222,13 +222,33 @@ ec_status ec_encode(const ec_program *prog, const uint8_t *const *data, uint8_t 
 ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uint8_t *const *recovered,
                     size_t block_bytes, ec_stream stream);
 
-/* Copy the program's records to the current device now (synchronously, one
- * small allocation per device and program).  Otherwise the first launch on
- * a device does it, which a latency-sensitive caller may not want.  Once a
- * program is on the device, ec_encode / ec_decode with it only enqueue one
- * kernel and may be captured into a HIP graph.
+/* Copy the program's records to the current device now (synchronously).
+ * Otherwise the first launch on a device does it, which a latency-sensitive
+ * caller may not want.  Once a program is on the device, ec_encode /
+ * ec_decode with it only enqueue one kernel and may be captured into a HIP
+ * graph.
+ * Records live in the device's program pool: device memory taken in chunks
+ * of at least 4 MiB (kept until the process ends) and shared by all
+ * programs, where identical records are stored once.  ec_program_free drops
+ * the program's hold on its records; their space is reused once no program
+ * holds them.
  * Errors: EC_ERR_ARG, EC_ERR_NOMEM, EC_ERR_DEVICE. */
 ec_status ec_program_upload(ec_program *prog);
+
+/* Copy the records of n programs (each non-null) to the current device: the
+ * pool first sets aside, in one piece, the space that all of those not yet
+ * there need, so a set of programs takes at most one device allocation
+ * (a server's hundreds of erasure patterns, say).  Programs already on the
+ * device are skipped.  Synchronous.
+ * Errors: EC_ERR_ARG (n < 0, a null pointer), EC_ERR_NOMEM, EC_ERR_DEVICE;
+ * on an error the programs before the failing one stay uploaded. */
+ec_status ec_program_upload_many(ec_program *const *progs, int n);
+
+/* The current device's program pool: chunks of device memory allocated,
+ * distinct records held, and bytes of them in use (in 256-byte granules).
+ * Any output pointer may be null, not all three (EC_ERR_ARG).
+ * EC_ERR_DEVICE if there is no current device. */
+ec_status ec_program_pool_stats(int *chunks, int *images, size_t *bytes_used);
 
 void ec_program_free(ec_program *prog);
 const char *ec_status_str(ec_status s);

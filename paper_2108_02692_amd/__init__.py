@@ -117,6 +117,9 @@ def lib():
         L.ec_stripe_stream.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int,
                                        ctypes.c_size_t, vp]
         L.ec_program_upload.argtypes = [vp]
+        L.ec_program_upload_many.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.ec_program_pool_stats.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_size_t)]
         L.ec_batch_reserve.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
         L.ec_batch_build.argtypes = [ctypes.POINTER(Stripe), ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.ec_batch_launch.argtypes = [vp, vp]
@@ -137,7 +140,7 @@ def lib():
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
                      "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_program_part_bytecode", "ec_batch_build", "ec_device_copy",
                      "ec_stripe_stream", "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set",
-                     "ec_batch_run_noalloc",
+                     "ec_batch_run_noalloc", "ec_program_upload", "ec_program_upload_many", "ec_program_pool_stats",
                      "ec_server_create", "ec_server_run"):
             getattr(L, name).restype = st
         _lib = L
@@ -304,6 +307,22 @@ def ec_decode(prog: Program, survivors, recovered, block_bytes: int, stream=None
     in ``prog.out_blocks`` order."""
     _check(lib().ec_decode(prog.handle, _ptr_array(survivors), _ptr_array(recovered), block_bytes,
                            _stream_handle(stream)), "ec_decode")
+
+
+def ec_program_upload_many(progs):
+    """Copy many programs' records to the current device, setting aside the
+    space they need in one piece first (at most one device allocation)."""
+    progs = list(progs)
+    arr = (ctypes.c_void_p * max(1, len(progs)))(*[p.handle for p in progs])
+    _check(lib().ec_program_upload_many(arr, len(progs)), "ec_program_upload_many")
+
+
+def ec_program_pool_stats():
+    """(chunks, distinct records, bytes in use) of the current device's
+    program pool."""
+    c, i, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+    _check(lib().ec_program_pool_stats(ctypes.byref(c), ctypes.byref(i), ctypes.byref(b)), "ec_program_pool_stats")
+    return c.value, i.value, b.value
 
 
 def ec_device_copy(dst, src, nbytes: int, stream=None):

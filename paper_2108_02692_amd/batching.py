@@ -16,7 +16,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import LEVEL_PLAIN, SCHED_PUSH, ec_batch_build, ec_compile_slp, ec_matrix_cauchy
+from . import LEVEL_PLAIN, SCHED_PUSH, ec_batch_build, ec_compile_slp, ec_matrix_cauchy, ec_program_upload_many
 
 CODECS_DEFAULT = ((6, 3), (10, 4), (12, 4), (14, 4))
 
@@ -78,11 +78,11 @@ class ProgramCache:
             list(ex.map(lambda k: self.get(*k), keys))
 
     def upload(self):
-        """Copy every cached program's records to the current device."""
+        """Copy every cached program's records to the current device (one
+        device allocation at most for all of them)."""
         with self._lock:
             progs = list(self._progs.values())
-        for prog in progs:
-            prog.upload()
+        ec_program_upload_many(progs)
 
     def all_patterns(self, n, p):
         return [()] + [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]

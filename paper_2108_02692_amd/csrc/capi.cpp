@@ -569,6 +569,36 @@ ec_status ec_program_upload(ec_program *prog) {
   return prog->device_words(&st) ? EC_OK : st;
 }
 
+ec_status ec_program_upload_many(ec_program *const *progs, int n) {
+  if (n < 0 || (n > 0 && !progs)) return EC_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!progs[i]) return EC_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
+  std::vector<const std::vector<uint32_t> *> need;
+  for (int i = 0; i < n; ++i)
+    if (!progs[i]->device_words_present(dev)) need.push_back(&progs[i]->image);
+  if (need.empty()) return EC_OK;
+  const size_t bytes = ec::pool_missing_bytes(dev, need);
+  if (bytes) {
+    const ec_status st = ec::pool_reserve(dev, bytes);
+    if (st != EC_OK) return st;
+  }
+  for (int i = 0; i < n; ++i) {
+    ec_status st = EC_OK;
+    if (!progs[i]->device_words(dev, &st)) return st;
+  }
+  return EC_OK;
+}
+
+ec_status ec_program_pool_stats(int *chunks, int *images, size_t *bytes_used) {
+  if (!chunks && !images && !bytes_used) return EC_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
+  ec::pool_stats(dev, chunks, images, bytes_used);
+  return EC_OK;
+}
+
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words) {
   if (!prog || !words || !n_words || part < 0) return EC_ERR_ARG;
   const int nb = (int)prog->parts.size();

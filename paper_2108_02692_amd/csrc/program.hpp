@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/ec.h"
+#include "program_pool.hpp"
 #include "push.hpp"
 #include "slp.hpp"
 
@@ -38,20 +39,14 @@ struct ec_program {
   int split = EC_SPLIT_AUTO;
   ec_program_info info{};
   std::mutex mu;
-  std::map<int, uint32_t *> dev_words;  // device -> bytecode copy
+  std::map<int, const uint32_t *> dev_words;  // device -> bytecode copy (in the device's program pool)
   // the same pointers for the first kDevCache device ids, read without the
   // lock (a batch looks up every stripe's program on every launch)
   static constexpr int kDevCache = 16;
   std::atomic<const uint32_t *> dev_cache[kDevCache] = {};
 
   ~ec_program() {
-    for (auto &kv : dev_words) {
-      int cur = 0;
-      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
-        (void)hipFree(kv.second);
-        (void)hipSetDevice(cur);
-      }
-    }
+    for (auto &kv : dev_words) ec::pool_release(kv.first, kv.second);
   }
 
   // Builds the whole-matrix CO/FU/SCHED stages of the program's level once.
@@ -85,20 +80,15 @@ struct ec_program {
   }
 
   // Device copy of the bytecode for device `dev`, the current device
-  // (uploaded once).
+  // (placed in the device's program pool once, shared with identical
+  // images).
   const uint32_t *device_words(int dev, ec_status *st) {
     if (const uint32_t *p = device_words_present(dev)) return p;
     std::lock_guard<std::mutex> g(mu);
     auto it = dev_words.find(dev);
     if (it != dev_words.end()) return it->second;
-    uint32_t *d = nullptr;
-    const size_t bytes = image.size() * sizeof(uint32_t);
-    if (hipMalloc((void **)&d, bytes) != hipSuccess) { *st = EC_ERR_NOMEM; return nullptr; }
-    if (hipMemcpy(d, image.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-      (void)hipFree(d);
-      *st = EC_ERR_DEVICE;
-      return nullptr;
-    }
+    const uint32_t *d = ec::pool_acquire(dev, image, st);
+    if (!d) return nullptr;
     dev_words[dev] = d;
     if (dev >= 0 && dev < kDevCache) dev_cache[dev].store(d, std::memory_order_release);
     return d;

@@ -170,9 +170,12 @@ ec_status ec_server_run(ec_server *sv, const ec_request *reqs, int n_reqs, int r
   // starts: nothing below allocates.
   std::sort(progs.begin(), progs.end());
   progs.erase(std::unique(progs.begin(), progs.end()), progs.end());
-  for (const ec_program *p : progs) {
-    ec_status st = EC_OK;
-    if (!const_cast<ec_program *>(p)->device_words(&st)) return st;
+  {
+    // one device allocation at most for all of them
+    std::vector<ec_program *> mut;
+    for (const ec_program *p : progs) mut.push_back(const_cast<ec_program *>(p));
+    const ec_status st = ec_program_upload_many(mut.data(), (int)mut.size());
+    if (st != EC_OK) return st;
   }
   // Work items of one batch: at most one per tile of each request's strips,
   // or, with a row split, one per resident wave (fewer than 8192).

@@ -39,7 +39,7 @@ def run_driver(exe, cwd):
 
 @pytest.mark.slow
 def test_library_host_code_sanitized(tmp_path):
-    srcs = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp"]
+    srcs = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp"]
     inc = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
     jobs = [(["g++"] + inc + SAN + ["-c", os.path.join(CSRC, s), "-o", s + ".o"]) for s in srcs]
     jobs.append(["g++"] + inc + SAN + ["-c", os.path.join(HERE, "sanitize", "lib_driver.cpp"), "-o", "drv.o"])
