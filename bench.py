@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-block-mib", type=int, default=32, help="oracle sample: 10 blocks of this size")
     ap.add_argument("--only", choices=["all", "compressed", "plain", "decode", "copy", "batched", "serve",
-                                       "decode_all", "codecs", "small", "schedulers", "batched_programs"],
+                                       "decode_all", "codecs", "small", "schedulers", "batched_programs", "staged"],
                     default="all",
                     help="time one kernel only (for profiler runs)")
     ap.add_argument("--calib", action="store_true",
@@ -230,6 +230,9 @@ def main():
     if args.only == "schedulers":
         print(json.dumps({"schedulers": bench_schedulers(args, stream, gen, data, parity)}), flush=True)
         return
+    if args.only == "staged":
+        print(json.dumps({"staged": bench_staged(args, stream, gen, data, parity)}), flush=True)
+        return
     res = {}
     if args.only in ("all", "compressed"):
         res["compressed"] = measure(comp, data, parity)
@@ -294,6 +297,8 @@ def main():
     if args.only == "all":
         log("strip schedulers ...")
         extra["schedulers"] = bench_schedulers(args, stream, gen, data, parity)
+        log("staged launches ...")
+        extra["staged"] = bench_staged(args, stream, gen, data, parity)
     head = "compressed" if "compressed" in res else "plain"
     hprog = comp if head == "compressed" else plain
     ms = res[head]
@@ -404,6 +409,42 @@ def bench_schedulers(args, stream, gen, data, parity):
                                      "records": r["records"], "ops": r["ops"]} for r in table]})
         log("%s: %s" % (what, ", ".join("%s/%s %.4f ms" % (r["level"], name[r["scheduler"]], r["ms"])
                                          for r in table)))
+    return rows
+
+
+def bench_staged(args, stream, gen, data, parity):
+    """The staged launch (each tile's input strips copied into LDS by one
+    workgroup, its 4 waves on a quarter of the rows each) against the direct
+    one (one wave per tile streaming strips into its registers), the same
+    program level and defaults otherwise: RS(10,4) encode and the {2,4,5,6}
+    decode of 10 x 64 MiB (the data above), and encodes of 10 x 8 MiB and
+    10 x 1 MiB."""
+    import paper_2108_02692_amd as E
+    from paper_2108_02692_amd import workloads as W
+    n, p = 10, 4
+    S = data[0].numel()
+    E.ec_encode(E.ec_compile_slp(n, p, gen), data, parity, S, stream)
+    blocks = data + parity
+    rec = W.empty_blocks(4, S)
+    dec_in = [blocks[i] for i in E.ec_compile_slp(n, p, gen, [2, 4, 5, 6]).in_blocks]
+    mid, mid_par = W.device_blocks(n, 8 << 20, seed=0), W.empty_blocks(p, 8 << 20)
+    small, small_par = W.device_blocks(n, 1 << 20, seed=0), W.empty_blocks(p, 1 << 20)
+    cases = (("RS(10,4) encode 10 x 64 MiB", (), data, parity, S),
+             ("RS(10,4) decode {2,4,5,6} 10 x 64 MiB", [2, 4, 5, 6], dec_in, rec, S),
+             ("RS(10,4) encode 10 x 8 MiB", (), mid, mid_par, 8 << 20),
+             ("RS(10,4) encode 10 x 1 MiB", (), small, small_par, 1 << 20))
+    rows = []
+    for what, er, ins, outs, bb in cases:
+        row = {"workload": what}
+        for level, lname in ((E.LEVEL_CO_FU_SCHED, "compressed"), (E.LEVEL_PLAIN, "plain")):
+            for split, sname in ((E.SPLIT_AUTO, "direct"), (E.SPLIT_STAGED, "staged")):
+                prog = E.ec_compile_slp(n, p, gen, list(er), level=level, split=split)
+                run = (E.ec_decode if er else E.ec_encode)
+                ms = time_launches(lambda: run(prog, ins, outs, bb, stream), args.steps, args.warmup, stream)
+                row["%s_%s" % (lname, sname)] = {"ms": ms, "hbm_frac": (n + len(outs)) * bb / ms / 1e6 / HBM_PEAK_GBS,
+                                                 "slots": prog.info["slots"]}
+        rows.append(row)
+        log("%s: %s" % (what, ", ".join("%s %.4f ms" % (k, v["ms"]) for k, v in row.items() if k != "workload")))
     return rows
 
 

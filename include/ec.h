@@ -140,8 +140,28 @@ enum {
   EC_SPLIT_ALWAYS = 2, /* block parts on every launch when the program has them */
   EC_SPLIT_ROWS = 3,   /* row parts on every launch when the program has them */
   EC_SPLIT_PAIRS = 4,  /* pair parts on every launch when the program has them */
-  EC_SPLIT_PASSES = 5  /* pass parts on every launch when the program has them */
+  EC_SPLIT_PASSES = 5, /* pass parts on every launch when the program has them */
+  EC_SPLIT_STAGED = 6  /* stage parts in LDS (below); only these parts are built */
 };
+
+/* Staged launches (EC_SPLIT_STAGED; Sec. 8's multi-level hierarchy and
+ * software prefetch, with LDS as the level between the register slots and
+ * HBM).  The program carries "stage parts": up to 4 runs of consecutive bit
+ * rows, min(4, 8 n_out) of them, as even as can be, each scheduled from the
+ * program itself (its level, order and slot budget).  A launch runs one
+ * workgroup of 4 waves per tile: the waves copy the tile's 8 n_in input
+ * strip-tiles (1 KiB each) into LDS with asynchronous LDS-DMA loads, then
+ * wave w runs stage part w with its strip loads served from LDS.  Every
+ * input strip-tile is read from HBM once per tile, and a part's slots hold
+ * only its own rows.  Needs 8 KiB of LDS per input block: n_in <= 20
+ * (EC_ERR_UNSUPPORTED at compile time beyond, or at launch on a device with
+ * less LDS per workgroup).  Off by default: measured on RS(10,4), it
+ * fetches exactly the algorithmic bytes at every size (the default split of
+ * short stripes re-reads inputs across its parts) but, its waves loading
+ * nearly every input for a quarter of the rows at 2 waves per SIMD, runs
+ * 1.3-2.4x slower than the direct launch from 8 MiB blocks up and within 5%
+ * of it at 1 MiB.  A batch runs a staged program whole, one wave per
+ * tile. */
 
 typedef struct {
   uint32_t n, p;        /* codec */
@@ -166,6 +186,7 @@ typedef struct {
   uint32_t n_pair_parts; /* pair parts for the row split (0: none) */
   uint32_t n_pass_parts; /* pass parts (0: none; the program needs one pass) */
   uint32_t scheduler;   /* EC_SCHED_* the strip order was made with */
+  uint32_t n_stage_parts; /* stage parts (EC_SPLIT_STAGED only; 0: none) */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
 } ec_program_info;
@@ -312,7 +333,8 @@ ec_status ec_program_bytecode(const ec_program *prog, const uint32_t **words, si
  * 0 <= part < info.n_parts, then row part `part - n_parts` for
  * part < n_parts + n_row_parts, then pair part `part - n_parts -
  * n_row_parts` up to n_parts + n_row_parts + n_pair_parts, then the pass
- * parts up to that plus n_pass_parts (host copy; same record format as
+ * parts up to that plus n_pass_parts, then the stage parts up to that plus
+ * n_stage_parts (host copy; same record format as
  * ec_program_bytecode, storing only the part's output rows).  EC_ERR_ARG for
  * a part that does not exist. */
 ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint32_t **words, size_t *n_words);

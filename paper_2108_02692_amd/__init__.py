@@ -22,12 +22,13 @@ __all__ = [
     "Server", "ec_server_create",
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
-    "SPLIT_ROWS", "SPLIT_PAIRS", "SPLIT_PASSES", "SCHED_PUSH", "SCHED_GREEDY",
+    "SPLIT_ROWS", "SPLIT_PAIRS", "SPLIT_PASSES", "SPLIT_STAGED", "SCHED_PUSH", "SCHED_GREEDY",
+    "ec_program_upload_many", "ec_program_pool_stats",
 ]
 
 LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
 COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
-SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS, SPLIT_ROWS, SPLIT_PAIRS, SPLIT_PASSES = 0, 1, 2, 3, 4, 5
+SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS, SPLIT_ROWS, SPLIT_PAIRS, SPLIT_PASSES, SPLIT_STAGED = 0, 1, 2, 3, 4, 5, 6
 SCHED_PUSH, SCHED_GREEDY = 0, 1
 STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
 
@@ -59,7 +60,7 @@ class ProgramInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
         "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts",
-        "n_row_parts", "n_pair_parts", "n_pass_parts", "scheduler")] + [
+        "n_row_parts", "n_pair_parts", "n_pass_parts", "scheduler", "n_stage_parts")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
 
 
@@ -274,8 +275,8 @@ class Program:
     def part_bytecode(self, part: int):
         """Words of row-split part ``part``: block parts first
         (``part < info["n_parts"]``), then row parts, then pair parts, then
-        pass parts (up to ``n_parts + n_row_parts + n_pair_parts +
-        n_pass_parts``)."""
+        pass parts, then stage parts (up to ``n_parts + n_row_parts +
+        n_pair_parts + n_pass_parts + n_stage_parts``)."""
         w = ctypes.POINTER(ctypes.c_uint32)()
         n = ctypes.c_size_t()
         _check(lib().ec_program_part_bytecode(self._h, part, ctypes.byref(w), ctypes.byref(n)),

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libec.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp", "exec.hip", "noalloc.hip", "ceiling.hip"]
+SOURCES = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp", "exec.hip", "staged.hip", "noalloc.hip", "ceiling.hip"]
 # Packed FP32 instructions are disabled for all device code (none is used).
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]

@@ -12,6 +12,7 @@
 #include "../../include/ec.h"
 #include "bytecode.hpp"
 #include "exec.hpp"
+#include "staged.hpp"
 #include "gf.hpp"
 #include "push.hpp"
 #include "slp.hpp"
@@ -108,6 +109,43 @@ void set_blocks(ExecArgs &a, const uint8_t *const *in, int n_in, uint8_t *const 
   a.seg_tiles = a.n_tiles >> a.seg_shift;
 }
 
+// LDS of the current device: per workgroup and per compute unit (bytes).
+bool device_lds(int *per_group, int *per_cu) {
+  static std::mutex mu;
+  static std::map<int, std::pair<int, int>> lds;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = lds.find(dev);
+  if (it == lds.end()) {
+    int a = 0, b = 0;
+    if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+      return false;
+    it = lds.emplace(dev, std::make_pair(a, b)).first;
+  }
+  *per_group = it->second.first;
+  *per_cu = it->second.second;
+  return true;
+}
+
+// A staged launch: one workgroup per tile at a time, its waves on the stage
+// parts; as many workgroups as the LDS (8 KiB per input block each) and the
+// registers let stay resident, each looping over tiles.
+ec_status launch_staged(const ec_program *prog, ExecArgs &a, int n_cus, ec_stream stream) {
+  const uint64_t lds_bytes = (uint64_t)a.n_in * kStageBytesPerBlock;
+  int per_group = 0, per_cu = 0;
+  if (!device_lds(&per_group, &per_cu)) return EC_ERR_DEVICE;
+  if (lds_bytes > (uint64_t)per_group || lds_bytes > (uint64_t)per_cu) return EC_ERR_UNSUPPORTED;
+  a.n_parts = (uint32_t)prog->stage_part_off.size();
+  for (uint32_t q = 0; q < a.n_parts; ++q) a.part_off[q] = prog->stage_part_off[q];
+  const uint64_t groups_per_cu =
+      std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)per_cu / lds_bytes, (uint64_t)waves_per_simd(prog->slots)));
+  const int grid = (int)std::min<uint64_t>(a.n_tiles, (uint64_t)n_cus * groups_per_cu);
+  if (staged_launch(prog->slots, a, grid, (uint32_t)lds_bytes, (hipStream_t)stream) != 0) return EC_ERR_DEVICE;
+  return EC_OK;
+}
+
 ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *const *out, size_t block_bytes,
                  ec_stream stream) {
   if (!prog || !in || !out) return EC_ERR_ARG;
@@ -121,6 +159,7 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   a.prog = words;
   const int n_cus = device_cus();
   if (n_cus <= 0) return EC_ERR_DEVICE;
+  if (prog->split == EC_SPLIT_STAGED) return launch_staged(prog, a, n_cus, stream);
   const uint64_t resident = (uint64_t)n_cus * waves_per_simd(prog->slots);  // workgroups of 4 waves
   // Row split for short stripes: single-row parts first, else pairs of
   // rows, else parts of whole output blocks.  Measured on RS(10,4) encodes
@@ -210,7 +249,9 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (o.scheduler > EC_SCHED_GREEDY) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
-  if (o.split > EC_SPLIT_PASSES) return EC_ERR_UNSUPPORTED;
+  if (o.split > EC_SPLIT_STAGED) return EC_ERR_UNSUPPORTED;
+  if (o.split == EC_SPLIT_STAGED && (uint64_t)n * kStageBytesPerBlock > kMaxStageBytes)
+    return EC_ERR_UNSUPPORTED;
 
   std::unique_ptr<ec_program> prog(new (std::nothrow) ec_program);
   if (!prog) return EC_ERR_NOMEM;
@@ -384,7 +425,8 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     }
     return true;
   };
-  if (o.split != EC_SPLIT_NEVER) {
+  const bool split_parts = o.split != EC_SPLIT_NEVER && o.split != EC_SPLIT_STAGED;
+  if (split_parts) {
     if (n_out > 1 && !build_parts(8, kMaxParts, prog->parts)) return EC_ERR_UNSUPPORTED;
     if (n_rows > 1 && !build_parts(1, kMaxRowParts, prog->row_parts)) return EC_ERR_UNSUPPORTED;
     if (n_rows > 2 && !build_parts(2, kMaxRowParts / 2, prog->pair_parts)) return EC_ERR_UNSUPPORTED;
@@ -399,7 +441,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   // caches the next).
   prog->pass_parts.clear();
   prog->pass_part_off.clear();
-  if (o.split != EC_SPLIT_NEVER && prog->code.passes > 1) {
+  if (split_parts && prog->code.passes > 1) {
     for (int groups = prog->code.passes; groups <= std::min(n_out, kMaxParts); ++groups) {
       std::vector<PushCode> set;
       bool fits = true;
@@ -421,6 +463,26 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
       }
     }
   }
+  // Stage parts: min(4, rows) runs of consecutive rows, one per wave of a
+  // staged workgroup, scheduled from the program itself on its budget.
+  // Their strip loads read LDS, so a part may take several passes (each
+  // re-reads the staged strips, not HBM) and no prefetch records are made.
+  prog->stage_parts.clear();
+  prog->stage_part_off.clear();
+  if (o.split == EC_SPLIT_STAGED) {
+    const int groups = std::min(kStageWaves, n_rows);
+    for (int g = 0; g < groups; ++g) {
+      PushOpts pp = po;
+      pp.prefetch = 0;
+      pp.row_lo = g * n_rows / groups;
+      pp.row_hi = (g + 1) * n_rows / groups;
+      PushCode part;
+      if (push_schedule(dag, n_in, pp, part) != 0) return EC_ERR_CAPACITY;
+      if (!simulate_code(part.words, prog->slots, n_in, n_out, brows, pp.row_lo, pp.row_hi))
+        return EC_ERR_UNSUPPORTED;
+      prog->stage_parts.push_back(std::move(part));
+    }
+  }
   for (const PushCode &part : prog->parts) {
     prog->part_off.push_back((uint32_t)prog->image.size());
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
@@ -435,6 +497,10 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   }
   for (const PushCode &part : prog->pass_parts) {
     prog->pass_part_off.push_back((uint32_t)prog->image.size());
+    prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
+  }
+  for (const PushCode &part : prog->stage_parts) {
+    prog->stage_part_off.push_back((uint32_t)prog->image.size());
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
@@ -463,6 +529,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_pair_parts = (uint32_t)prog->pair_parts.size();
   info.n_pass_parts = (uint32_t)prog->pass_parts.size();
   info.scheduler = o.scheduler;
+  info.n_stage_parts = (uint32_t)prog->stage_parts.size();
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -604,11 +671,13 @@ ec_status ec_program_part_bytecode(const ec_program *prog, int part, const uint3
   const int nb = (int)prog->parts.size();
   const int nr = (int)prog->row_parts.size();
   const int np = (int)prog->pair_parts.size();
-  if (part >= nb + nr + np + (int)prog->pass_parts.size()) return EC_ERR_ARG;
-  const PushCode &c = part < nb        ? prog->parts[part]
-                      : part < nb + nr ? prog->row_parts[part - nb]
+  const int ns = (int)prog->pass_parts.size();
+  if (part >= nb + nr + np + ns + (int)prog->stage_parts.size()) return EC_ERR_ARG;
+  const PushCode &c = part < nb             ? prog->parts[part]
+                      : part < nb + nr      ? prog->row_parts[part - nb]
                       : part < nb + nr + np ? prog->pair_parts[part - nb - nr]
-                                            : prog->pass_parts[part - nb - nr - np];
+                      : part < nb + nr + np + ns ? prog->pass_parts[part - nb - nr - np]
+                                                 : prog->stage_parts[part - nb - nr - np - ns];
   *words = c.words.data();
   *n_words = c.words.size();
   return EC_OK;

@@ -1,5 +1,6 @@
 #!/usr/bin/env python3
-"""Writes exec.hip, the gfx950 executor, from the tables below.
+"""Writes exec.hip, the gfx950 executor, and staged.hip, its variant that
+stages each tile in LDS, from the tables below.
 
 Run from this directory after changing it:  python3 gen_exec.py
 The record format it interprets is described in bytecode.hpp.
@@ -54,8 +55,10 @@ def asm_lines(lines):
 CLOBBERS = ", ".join('"s%d"' % r for r in range(36, 96)) + ', "scc"'
 
 
-def handler(K, kind, W, O, run_base, h_other):
-    """One record handler for window W (the next record is loaded into O)."""
+def handler(K, kind, W, O, run_base, h_other, lds=False):
+    """One record handler for window W (the next record is loaded into O).
+    lds: strips are read from the workgroup's staged copy of the tile in LDS
+    (ds_read_b128) instead of from global memory."""
     nxt = ["s_bfe_u32 s74, s%d, 0x7000c" % W,           # record bytes
            "s_add_u32 s68, s68, s74",
            "s_load_dwordx16 s[%d:%d], %%[prog], s68" % (O, O + 15)]
@@ -95,6 +98,30 @@ def handler(K, kind, W, O, run_base, h_other):
            "s_add_u32 s80, s%d, s74" % run_base,
            "s_addc_u32 s81, s%d, 0" % (run_base + 1),
            "s_setpc_b64 s[80:81]"]
+    # staged: strip (block b, strip c) of the tile sits at LDS byte
+    # lbase + (8 b + c) * 1 KiB, lane l's 16 bytes at + 16 l; the address
+    # goes through the spare register (no prefetch records run here)
+    laddr = ["s_bfe_u32 s74, s%d, 0x50013" % (W + 1),  # block
+             "s_bfe_u32 s75, s%d, 0x30018" % (W + 1),  # strip of the block
+             "s_lshl3_add_u32 s74, s74, s75",
+             "s_lshl_b32 s74, s74, 10",
+             "s_add_u32 s74, s74, %[lbase]",
+             "v_add_u32_e32 v%d, s74, %%[voff]" % (4 + 4 * K)]
+    if lds:
+        # an LDS read completes within its record (the window's wait for
+        # lgkmcnt(0) also covers it), so the wait records have nothing to do
+        # and the prefetch records are skipped
+        body = {
+            0: nxt + run,
+            1: nxt + pull + run,
+            2: nxt + pull + laddr + ld + run,
+            3: nxt + pull + run,
+            4: nxt + pull + addr + store + run,
+            5: nxt + laddr + ld + run,
+            6: ["s_branch 99f"],
+            7: nxt + run,
+        }[kind]
+        return [".p2align 9"] + body
     body = {
         0: nxt + run,
         1: nxt + wait + pull + run,
@@ -123,7 +150,7 @@ def run_table(W, O, h_other):
     return lines
 
 
-def program_asm(K):
+def program_asm(K, lds=False):
     L = ["s_mov_b32 s68, 0",
          "s_load_dwordx16 s[%d:%d], %%[prog], 0x0" % (WA, WA + 15),
          "s_getpc_b64 s[82:83]",
@@ -137,7 +164,7 @@ def program_asm(K):
           "s_setpc_b64 s[80:81]"]
     for W, O, run_base, h_other, label in ((WA, WB, 88, 86, 91), (WB, WA, 90, 84, 92)):
         for kind in range(8):
-            h = handler(K, kind, W, O, run_base, h_other)
+            h = handler(K, kind, W, O, run_base, h_other, lds)
             if kind == 0:
                 h = h[:1] + ["%d:" % label] + h[1:]
             L += h
@@ -145,8 +172,12 @@ def program_asm(K):
     L += ["94:"] + run_table(WB, WA, 84)
     L += ["95:"]
     for k in range(K):
-        L += ["global_load_dwordx4 v[%d:%d], %%[voff], s[72:73] nt" % (4 + 4 * k, 7 + 4 * k),
-              "s_setpc_b64 s[78:79]", "s_nop 0"]
+        if lds:  # 8 + 4 + 4 bytes, like the global entry
+            L += ["ds_read_b128 v[%d:%d], v%d" % (4 + 4 * k, 7 + 4 * k, 4 + 4 * K),
+                  "s_setpc_b64 s[78:79]", "s_nop 0"]
+        else:
+            L += ["global_load_dwordx4 v[%d:%d], %%[voff], s[72:73] nt" % (4 + 4 * k, 7 + 4 * k),
+                  "s_setpc_b64 s[78:79]", "s_nop 0"]
     L += ["96:"]
     for k in range(MAX_WAIT + 1):
         L += ["s_waitcnt vmcnt(%d)" % k, "s_setpc_b64 s[78:79]"]
@@ -154,7 +185,7 @@ def program_asm(K):
     return L
 
 
-HEAD = r'''// exec.hip -- gfx950 executor for push-form XOR programs.
+INTRO = r'''// exec.hip -- gfx950 executor for push-form XOR programs.
 // GENERATED by gen_exec.py -- edit that file and regenerate.
 //
 // One wave runs the whole program, or one row-split part of it, on one tile:
@@ -176,7 +207,9 @@ HEAD = r'''// exec.hip -- gfx950 executor for push-form XOR programs.
 //    counts, through a 64-entry table.
 // Temporaries never leave the registers (the deforestation of Sec. 5); the
 // host validates every record before the program reaches the device.
-#include <hip/hip_runtime.h>
+'''
+
+DEFS = r'''#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -210,6 +243,9 @@ typedef const __attribute__((address_space(4))) StripeDesc *ConstDescPtr;
 typedef const __attribute__((address_space(4))) uint32_t *ConstU32Ptr;
 
 '''
+
+HEAD = INTRO + DEFS
+
 
 PER_K = r'''// ---- %(K)d slots
 #define EC_INIT_%(K)d asm volatile(%(INIT)s : %(OUT)s)
@@ -321,6 +357,86 @@ int batch_launch(int slots, const BatchArgs &a, int grid, hipStream_t stream) {
 '''
 
 
+STAGED_INTRO = r'''// staged.hip -- gfx950 executor with each tile staged in LDS.
+// GENERATED by gen_exec.py -- edit that file and regenerate.
+//
+// The 4 waves of a workgroup share one tile (1 KiB of every strip): they
+// copy its input strip-tiles from global memory into LDS with LDS-DMA loads
+// (global_load_lds_dwordx4: 16 B per lane, non-temporal), meet at a
+// barrier, and each runs one part of the program, a quarter of the output
+// rows, through the interpreter of exec.hip, whose strip loads here read the
+// staged copy (ds_read_b128) instead of global memory; outputs are stored
+// from the registers as there.  A second barrier ends the tile before the
+// next one is staged.  Every input strip-tile leaves HBM once per tile
+// whatever the number of parts, and a part's register slots hold only its
+// own rows and temporaries: LDS is one more level between the registers and
+// HBM (the multi-level hierarchy of Sec. 8), with the workgroups that share
+// a compute unit overlapping one's staging with another's compute.
+'''
+
+PER_K_STAGED = r'''// ---- %(K)d slots
+#define EC_INIT_%(K)d asm volatile(%(INIT)s : %(OUT)s)
+#define EC_SRUN_%(K)d(prog_, voff_, tlo_, thi_, sl_, lbase_)  \
+  asm volatile(                                  \
+%(PROGRAM)s
+      : %(INOUT)s                                \
+      : [prog] "s"(prog_), [voff] "v"(voff_), [tlo] "v"(tlo_), [thi] "v"(thi_), [sl] "s"(sl_), \
+        [lbase] "s"(lbase_)                      \
+      : %(CLOB)s, "m0", "memory")
+
+__global__ void __launch_bounds__(256) slp_staged_kernel_%(K)d(ExecArgs a) {
+  extern __shared__ v4u stage[];  // 8 strip-tiles of 1 KiB per input block
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint64_t tab = lane < (uint32_t)kMaxBlocks ? a.blk[lane] : 0ull;
+  asm volatile("s_waitcnt vmcnt(0)" : "+v"(tab));
+  const uint32_t voff = lane * 16u;
+  const uint32_t sl = (uint32_t)a.strip_len;
+  const uint32_t n_strips = a.n_in * 8u;
+  // wave w runs part w; waves beyond the parts only stage
+  const bool runs = wave < a.n_parts;
+  const uint32_t *pk = a.prog + a.part_off[runs ? wave : 0u];
+  const uint32_t lbase = (uint32_t)(uintptr_t)stage;
+  %(DECLS)s
+  EC_INIT_%(K)d;
+  for (uint32_t kt = blockIdx.x; kt < a.n_tiles; kt += gridDim.x) {
+    const uint32_t tile = tile_of(kt, a.seg_shift, a.seg_mask, a.seg_tiles);
+    const uint64_t toff = (uint64_t)tile * kTileBytes;
+    const uint64_t t = tile_table(tab, toff);
+    const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+    if (toff + voff < sl) {
+      // strip-tile s = 8 b + c (block b, strip c) goes to stage[64 s ..]
+      for (uint32_t s = wave; s < n_strips; s += 4u) {
+        const uint32_t b = s >> 3;
+        const uint64_t base = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)thi, (int)b) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)tlo, (int)b);
+        const uint64_t src = base + (uint64_t)(s & 7u) * sl + voff;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(uintptr_t)src,
+                                         (__attribute__((address_space(3))) void *)(stage + 64u * s), 16, 0,
+                                         kStageNonTemporal);
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (runs && toff + voff < sl) EC_SRUN_%(K)d(pk, voff, tlo, thi, sl, lbase);
+    __syncthreads();
+  }
+}
+
+'''
+
+STAGED_TAIL = r'''int staged_launch(int slots, const ExecArgs &a, int grid, uint32_t lds_bytes, hipStream_t stream) {
+  switch (slots) {
+%(CASES)s
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace ec
+'''
+
+
 def writelanes():
     """Lane b of (tab_lo, tab_hi) <- block b's pointer (v_writelane with an
     immediate lane: no per-lane compare masks)."""
@@ -338,7 +454,9 @@ def init_asm(K):
     return '"' + "\\n\\t".join(regs) + '"'
 
 
-def main():
+def main(out_dir=None):
+    """Writes exec.hip and staged.hip into out_dir (default: beside this
+    file)."""
     out = HEAD % {"MAX_OPS": MAX_OPS, "STEP": STEP_BYTES, "MAXW": MAX_WAIT}
     for K in SLOT_BUDGETS:
         prog = "\n".join('      "%s\\n\\t"                     \\' % l for l in program_asm(K))
@@ -351,9 +469,25 @@ def main():
         "    case %d: hipLaunchKernelGGL(slp_batch_kernel_%d, dim3(grid), dim3(256), 0, stream, a); break;" % (K, K)
         for K in SLOT_BUDGETS)
     out += TAIL % {"EXEC_CASES": exec_cases, "BATCH_CASES": batch_cases}
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "exec.hip")
-    with open(path, "w") as f:
+    here = out_dir or os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "exec.hip"), "w") as f:
         f.write(out)
+
+    staged_defs = DEFS.replace('#include "exec.hpp"\n', '#include "exec.hpp"\n#include "staged.hpp"\n')
+    staged = STAGED_INTRO + staged_defs % {"MAX_OPS": MAX_OPS, "STEP": STEP_BYTES, "MAXW": MAX_WAIT}
+    staged += "// cache policy of the staging loads: non-temporal (each strip-tile is read once)\n"
+    staged += "constexpr int kStageNonTemporal = 2;\n\n"
+    for K in SLOT_BUDGETS:
+        prog = "\n".join('      "%s\\n\\t"                     \\' % l for l in program_asm(K, lds=True))
+        staged += PER_K_STAGED % {"K": K, "INIT": init_asm(K), "OUT": operands(K, "out"),
+                                  "INOUT": operands(K, "inout"), "PROGRAM": prog, "CLOB": CLOBBERS,
+                                  "DECLS": decls(K)}
+    cases = "\n".join(
+        "    case %d: hipLaunchKernelGGL(slp_staged_kernel_%d, dim3(grid), dim3(256), lds_bytes, stream, a); break;"
+        % (K, K) for K in SLOT_BUDGETS)
+    staged += STAGED_TAIL % {"CASES": cases}
+    with open(os.path.join(here, "staged.hip"), "w") as f:
+        f.write(staged)
 
 
 if __name__ == "__main__":

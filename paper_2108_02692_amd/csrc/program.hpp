@@ -31,11 +31,13 @@ struct ec_program {
   std::vector<ec::PushCode> row_parts;   // row-split parts of single rows or small row groups
   std::vector<ec::PushCode> pair_parts;  // row-split parts of row pairs (or small groups of pairs)
   std::vector<ec::PushCode> pass_parts;  // one pass each, when the program needs several (empty: none)
-  std::vector<uint32_t> image;           // device image: code.words, then parts, row_parts, pair_parts, pass_parts
+  std::vector<ec::PushCode> stage_parts; // runs of rows for the staged launch (EC_SPLIT_STAGED only)
+  std::vector<uint32_t> image;           // device image: code.words, then parts, row_parts, pair_parts, pass_parts, stage_parts
   std::vector<uint32_t> part_off;        // word offset of each part in the image
   std::vector<uint32_t> row_part_off;    // word offset of each row part in the image
   std::vector<uint32_t> pair_part_off;   // word offset of each pair part in the image
   std::vector<uint32_t> pass_part_off;   // word offset of each pass part in the image
+  std::vector<uint32_t> stage_part_off;  // word offset of each stage part in the image
   int split = EC_SPLIT_AUTO;
   ec_program_info info{};
   std::mutex mu;

@@ -18,6 +18,7 @@ int exec_launch(int, const ExecArgs &, int, hipStream_t) { return -1; }
 int batch_launch(int, const BatchArgs &, int, hipStream_t) { return -1; }
 int copy_launch(const void *, void *, uint64_t, int, hipStream_t) { return -1; }
 int stream_launch(const ExecArgs &, uint32_t, int, hipStream_t) { return -1; }
+int staged_launch(int, const ExecArgs &, int, uint32_t, hipStream_t) { return -1; }
 }  // namespace ec
 
 static int failures = 0;

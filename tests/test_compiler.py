@@ -326,7 +326,7 @@ def test_compile_errors():
         E.ec_compile_slp(10, 4, gen, block_strips=81)
     assert e.value.name == "EC_ERR_ARG"
     with pytest.raises(E.EcError) as e:
-        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_PASSES + 1)
+        E.ec_compile_slp(10, 4, gen, split=E.SPLIT_STAGED + 1)
     assert e.value.name == "EC_ERR_UNSUPPORTED"
     with pytest.raises(E.EcError) as e:
         E.ec_compile_slp(30, 4, E.ec_matrix_cauchy(30, 4))
@@ -377,3 +377,54 @@ def test_row_split_parts_cover_the_rows(n, p, er, level):
         prog.part_bytecode(n4 + npass)
     with pytest.raises(E.EcError):
         prog.part_bytecode(-1)
+
+
+@pytest.mark.parametrize("n,p,er", [(10, 4, ()), (10, 4, (2, 4, 5, 6)), (6, 3, (1, 7)), (14, 4, (0, 13)),
+                                    (4, 12, ()), (20, 9, ()), (2, 1, ()), (1, 1, ()), (12, 6, ()),
+                                    (4, 12, tuple(range(1, 12)))])
+@pytest.mark.parametrize("level", [E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED])
+def test_stage_parts_cover_the_rows(n, p, er, level):
+    """A staged program carries min(4, rows) stage parts and no other parts;
+    run by the independent simulator, the parts store consecutive runs of
+    rows that differ in size by at most one, together every output strip
+    with the bitmatrix row's value, exactly once, and make no prefetch
+    records (their loads read LDS)."""
+    gen = E.ec_matrix_cauchy(n, p)
+    rows = oracle_rows(gen, n, p, er)
+    prog = E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_STAGED)
+    info = prog.info
+    n_rows = len(rows)
+    assert info["n_stage_parts"] == min(4, n_rows)
+    assert info["n_parts"] == info["n_row_parts"] == info["n_pair_parts"] == info["n_pass_parts"] == 0
+    got = {}
+    for q in range(info["n_stage_parts"]):
+        words = prog.part_bytecode(q)
+        part = simulate(words, info["slots"], len(prog.in_blocks), len(prog.out_blocks))
+        assert sorted(part) == list(range(len(got), len(got) + len(part)))
+        assert len(part) in (n_rows // info["n_stage_parts"], -(-n_rows // info["n_stage_parts"]))
+        got.update(part)
+        pc = 0
+        while True:
+            f = fields(words[pc], words[pc + 1])
+            assert f["kind"] != 7, "prefetch record in a stage part"
+            if f["kind"] == 6:
+                break
+            pc += f["bytes"] // 4
+    assert [got[o] for o in range(n_rows)] == rows
+    with pytest.raises(E.EcError):
+        prog.part_bytecode(info["n_stage_parts"])
+    # the whole program is still there (a batch runs it whole)
+    assert simulate(prog.bytecode(), info["slots"], len(prog.in_blocks), len(prog.out_blocks)) == \
+        {o: rows[o] for o in range(n_rows)}
+
+
+def test_staged_limits():
+    """Staging holds 8 KiB of LDS per input block: at most 20 input blocks."""
+    E.ec_compile_slp(20, 4, E.ec_matrix_cauchy(20, 4), split=E.SPLIT_STAGED, level=E.LEVEL_PLAIN)
+    for n, p in ((21, 2), (28, 4)):
+        with pytest.raises(E.EcError) as e:
+            E.ec_compile_slp(n, p, E.ec_matrix_cauchy(n, p), split=E.SPLIT_STAGED)
+        assert e.value.name == "EC_ERR_UNSUPPORTED"
+    with pytest.raises(E.EcError) as e:
+        E.ec_compile_slp(10, 4, E.ec_matrix_cauchy(10, 4), split=E.SPLIT_STAGED + 1)
+    assert e.value.name == "EC_ERR_UNSUPPORTED"

@@ -104,7 +104,8 @@ def test_reusable_batch_reserve_and_refill():
     batch.free()
 
 
-@pytest.mark.parametrize("split", [E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS, E.SPLIT_ROWS, E.SPLIT_PAIRS])
+@pytest.mark.parametrize("split", [E.SPLIT_AUTO, E.SPLIT_NEVER, E.SPLIT_ALWAYS, E.SPLIT_ROWS, E.SPLIT_PAIRS,
+                                   E.SPLIT_STAGED])
 def test_batch_edge_shapes_and_mixed_levels(split):
     """One batch holding the extremes: the widest codec (32 blocks), 1-block
     codecs, blocks of 128 B (one lane of one tile per strip) and ragged

@@ -92,6 +92,31 @@ def test_decode_64mib_every_byte(rs10_4_64mib, er):
         first_diff(got, blocks[e], "64 MiB decode %s block %d vs original" % (er, e))
 
 
+@pytest.mark.parametrize("level", [E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN])
+def test_staged_64mib_every_byte(rs10_4_64mib, level):
+    """The staged launch (tiles copied into LDS, one workgroup per tile) on
+    the 64 MiB encode and the {2,4,5,6} decode: every byte against the
+    oracle."""
+    n, p, S, G, data, host, par = rs10_4_64mib
+    gen = gen_rows(n, p)
+    enc = E.ec_compile_slp(n, p, gen, level=level, split=E.SPLIT_STAGED)
+    out = W.empty_blocks(p, S, fill=0xA5)
+    E.ec_encode(enc, data, out, S)
+    torch.cuda.synchronize()
+    for j in range(p):
+        first_diff(out[j].cpu().numpy(), par[j], "staged 64 MiB encode level %d parity %d" % (level, j))
+    del out
+    er = [2, 4, 5, 6]
+    blocks = host + par
+    dev = list(data) + W.to_device(par)
+    dec = E.ec_compile_slp(n, p, gen, er, level=level, split=E.SPLIT_STAGED)
+    rec = W.empty_blocks(len(er), S, fill=0xA5)
+    E.ec_decode(dec, [dev[i] for i in dec.in_blocks], rec, S)
+    torch.cuda.synchronize()
+    for j, e in enumerate(dec.out_blocks):
+        first_diff(rec[j].cpu().numpy(), blocks[e], "staged 64 MiB decode %s block %d" % (er, e))
+
+
 def test_segment_order_single_launch_and_batch():
     """RS(4,2) on 32 MiB blocks (4 MiB strips: the segment tile order),
     encode and a two-block decode, as single launches and as one-stripe
