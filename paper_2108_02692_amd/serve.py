@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import LEVEL_CO_FU_SCHED, ec_server_create
+from . import LEVEL_CO_FU_SCHED, ec_batch_build, ec_server_create
 from .batching import ProgramCache
 
 MAX_OBJECT = 64 << 20  # largest object served (bytes)
@@ -121,11 +121,48 @@ def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool
     return reqs
 
 
+def batched_reference(server, requests, chunk=8192, reps=3):
+    """The same requests through the batched path, with the server's own
+    programs: batches of up to ``chunk`` stripes (outputs in one separate
+    device buffer), launched back to back on one stream.  Returns GB/s of
+    input of the fastest of ``reps`` passes."""
+    import torch
+    out = torch.empty(sum(r.n_out * r.block_bytes for r in requests), dtype=torch.uint8, device="cuda")
+    base, off, stripes = out.data_ptr(), 0, []
+    for r in requests:
+        outs = [base + off + j * r.block_bytes for j in range(r.n_out)]
+        off += r.n_out * r.block_bytes
+        stripes.append((server.cache.get(r.n, r.p, r.erased), r.inputs, outs, r.block_bytes))
+    stream = torch.cuda.current_stream()
+    batches = [ec_batch_build(stripes[i:i + chunk], stream=stream) for i in range(0, len(stripes), chunk)]
+    best = float("inf")
+    try:
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for b in batches:
+                b.launch(stream)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+    finally:
+        for b in batches:
+            b.free()
+    return sum(r.n * r.block_bytes for r in requests) / best / 1e9
+
+
 def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=DEFAULT_MAX_BATCH,
-        slots=38, drain=True, server=None):
+        slots=38, drain=True, server=None, warm_up=None):
     """The serving benchmark at one arrival rate: throughput, latency
     percentiles and requests per launch; with ``drain``, the same requests
-    again all present at once (the capacity behind the latencies)."""
+    again all present at once (the capacity behind the latencies), and once
+    more through the batched path (``batched_reference``).  A drain takes a
+    few ms, all of it within the device's slower start after the near-idle
+    real-time run: the first drain follows that run directly
+    (``drain_cold_GB_s``); ``warm_up()``, if given, then keeps the device
+    busy for a while (the caller's choice of work, finished before it
+    returns) and the drain is run again (``drain_GB_s``)."""
     import torch
     pool_bytes = 1 << 30
     g = torch.Generator(device="cuda")
@@ -158,16 +195,25 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
            "budget_bytes": budget_bytes, "inflight_slots": n_slots, "max_batch": max_batch,
            "programs": len(server.cache), "setup_s": setup_s}
     if drain:
-        for r in reqs:
-            r.arrival, r.done = 0.0, -1.0
-        gc.collect()
-        gc.disable()
-        b0 = server.batches
-        try:
-            d = server.serve(reqs, realtime=False)
-        finally:
-            gc.enable()
-        torch.cuda.synchronize()
-        res.update({"drain_s": d, "drain_GB_s": in_bytes / d / 1e9, "drain_launches": server.batches - b0})
+        def drain_once():
+            for r in reqs:
+                r.arrival, r.done = 0.0, -1.0
+            gc.collect()
+            gc.disable()
+            b0 = server.batches
+            try:
+                d = server.serve(reqs, realtime=False)
+            finally:
+                gc.enable()
+            torch.cuda.synchronize()
+            return d, server.batches - b0
+        d, launches = drain_once()
+        res["drain_cold_GB_s"] = in_bytes / d / 1e9
+        if warm_up is not None:
+            warm_up()
+            d, launches = drain_once()
+        res.update({"drain_s": d, "drain_GB_s": in_bytes / d / 1e9, "drain_launches": launches})
+        ref = batched_reference(server, reqs)
+        res.update({"batched_same_GB_s": ref, "drain_vs_batched_same": in_bytes / d / 1e9 / ref})
     del pool
     return res
