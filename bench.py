@@ -552,7 +552,7 @@ def bench_serving(args, batched_GB_s=None):
             for _ in range(max(1, args.serve_runs))]
     res = dict(runs[0])
     keys = ("p50_ms", "p99_ms", "mean_ms", "drain_GB_s", "drain_cold_GB_s", "requests_per_launch",
-            "batched_same_GB_s", "drain_vs_batched_same")
+            "launch_size_p99", "requests_alone", "batched_same_GB_s", "drain_vs_batched_same")
     for k in keys:
         res[k] = float(np.median([r[k] for r in runs]))
     res["runs"] = [{k: r[k] for k in keys} for r in runs]
@@ -560,9 +560,12 @@ def bench_serving(args, batched_GB_s=None):
     for rate in (20e3, 100e3, 500e3, 2e6, 8e6):
         r = serve.run(duration_s=40000.0 / rate, rate=rate, seed=8, server=server, drain=False)
         sweep.append({k: r[k] for k in ("rate_req_s", "requests", "GB_s", "p50_ms", "p99_ms", "mean_ms",
-                                        "requests_per_launch", "batches")})
-        log("serving at %.0f req/s: %.1f GB/s, p50 %.3f ms, p99 %.3f ms, %.1f requests per launch"
-            % (rate, r["GB_s"], r["p50_ms"], r["p99_ms"], r["requests_per_launch"]))
+                                        "requests_per_launch", "launch_size_p50", "launch_size_p99",
+                                        "launch_size_max", "requests_alone", "batches")})
+        log("serving at %.0f req/s: %.1f GB/s, p50 %.3f ms, p99 %.3f ms, %.1f requests per launch "
+            "(p50 %d, p99 %d, max %d; %.0f%% of requests alone)"
+            % (rate, r["GB_s"], r["p50_ms"], r["p99_ms"], r["requests_per_launch"], r["launch_size_p50"],
+               r["launch_size_p99"], r["launch_size_max"], 100 * r["requests_alone"]))
     res["sweep"] = sweep
     # compiling and uploading the server's programs (every erasure pattern
     # of its codecs): the device allocations the upload made, the distinct

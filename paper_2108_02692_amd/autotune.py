@@ -2,9 +2,10 @@
 
 For a workload key (codec mix and size class, or one stripe's codec, erasure
 set and block size) it times every candidate (program level, register slot
-budget, strip scheduler and, for batches, tile width per work item) on the
-real launch, keeps the fastest and records it in a JSON cache so later runs
-reuse the choice without timing again.
+budget, strip scheduler and, for batches, tile width per work item: the
+unroll of the batch kernel's persistent loop, the consecutive tiles a wave
+runs per item) on the real launch, keeps the fastest and records it in a
+JSON cache so later runs reuse the choice without timing again.
 """
 from __future__ import annotations
 

@@ -187,11 +187,19 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     lat = np.array([r.done - r.arrival for r in reqs])
     in_bytes = sum(r.n * r.block_bytes for r in reqs)
     batches = server.batches - b0
+    # the requests of one launch share its completion stamp (taken once per
+    # launch), so grouping by it gives every launch's size
+    _, per_launch = np.unique(np.array([r.done for r in reqs]), return_counts=True)
     res = {"loop": "native", "requests": len(reqs), "rate_req_s": rate, "arrival_s": duration_s, "wall_s": wall,
            "GB_s": in_bytes / wall / 1e9, "in_bytes": in_bytes,
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
            "mean_ms": float(lat.mean() * 1e3), "batches": batches,
            "requests_per_launch": len(reqs) / max(1, batches),
+           # over launches: median, 99th percentile and largest launch; over
+           # requests: the share served by a launch of its own
+           "launch_size_p50": float(np.percentile(per_launch, 50)),
+           "launch_size_p99": float(np.percentile(per_launch, 99)), "launch_size_max": int(per_launch.max()),
+           "requests_alone": float(np.sum(per_launch == 1) / len(reqs)),
            "budget_bytes": budget_bytes, "inflight_slots": n_slots, "max_batch": max_batch,
            "programs": len(server.cache), "setup_s": setup_s}
     if drain:
