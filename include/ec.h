@@ -106,7 +106,24 @@ typedef struct {
   uint32_t split;        /* EC_SPLIT_*: whether a launch may run the output rows of one
                             tile on different waves (see ec_program_info.n_parts) */
   uint32_t scheduler;    /* EC_SCHED_*; default EC_SCHED_PUSH */
+  uint32_t native;       /* 1: also compile the program into a native kernel (below); default 0 */
 } ec_compile_opts;
+
+/* Native kernels (ec_compile_opts.native = 1).  The program's records, a
+ * fixed sequence of strip loads, register XORs and strip stores per tile,
+ * are also written out as straight-line gfx950 code with every register
+ * slot a fixed register group, and compiled at ec_compile_slp time with
+ * hiprtc (host only: no device needed; about 1-2 s for an RS(10,4)
+ * program).  A single-stripe launch that runs the whole program, one wave
+ * per tile (no row split: ec_encode / ec_decode of long stripes), then runs
+ * that kernel instead of the interpreter: the same loads, XORs and stores
+ * in the same order, with no record dispatch, register indexing or record
+ * loads, so about a third of the instructions, and device-scope stores.
+ * Split launches and batches keep the interpreter.  The kernel is loaded on
+ * a device at the program's upload or first launch there and stays loaded
+ * until the process ends (identical kernels are loaded once).  Not with
+ * EC_SPLIT_STAGED (EC_ERR_UNSUPPORTED); EC_ERR_UNSUPPORTED also if the
+ * compiler fails. */
 
 /* Row split.  Unless compiled with EC_SPLIT_NEVER, a program also carries
  * "parts": independent programs that each compute some of the output rows
@@ -187,6 +204,7 @@ typedef struct {
   uint32_t n_pass_parts; /* pass parts (0: none; the program needs one pass) */
   uint32_t scheduler;   /* EC_SCHED_* the strip order was made with */
   uint32_t n_stage_parts; /* stage parts (EC_SPLIT_STAGED only; 0: none) */
+  uint32_t native;      /* 1: the program has a native kernel */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
 } ec_program_info;
@@ -248,6 +266,7 @@ ec_status ec_decode(const ec_program *prog, const uint8_t *const *survivors, uin
  * caller may not want.  Once a program is on the device, ec_encode /
  * ec_decode with it only enqueue one kernel and may be captured into a HIP
  * graph.
+ * A program with a native kernel also loads that kernel here.
  * Records live in the device's program pool: device memory taken in chunks
  * of at least 4 MiB (kept until the process ends) and shared by all
  * programs, where identical records are stored once.  ec_program_free drops
@@ -264,6 +283,11 @@ ec_status ec_program_upload(ec_program *prog);
  * Errors: EC_ERR_ARG (n < 0, a null pointer), EC_ERR_NOMEM, EC_ERR_DEVICE;
  * on an error the programs before the failing one stay uploaded. */
 ec_status ec_program_upload_many(ec_program *const *progs, int n);
+
+/* The source of the program's native kernel (host copy, valid until
+ * ec_program_free; *len without a terminating zero, which follows it).
+ * EC_ERR_ARG if the program has none. */
+ec_status ec_program_native_source(const ec_program *prog, const char **src, size_t *len);
 
 /* The current device's program pool: chunks of device memory allocated,
  * distinct records held, and bytes of them in use (in 256-byte granules).

@@ -53,14 +53,15 @@ DEFAULT_PREFETCH = 0
 class CompileOpts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("slot_budget", ctypes.c_uint32),
                 ("compress", ctypes.c_uint32), ("block_strips", ctypes.c_uint32),
-                ("prefetch", ctypes.c_uint32), ("split", ctypes.c_uint32), ("scheduler", ctypes.c_uint32)]
+                ("prefetch", ctypes.c_uint32), ("split", ctypes.c_uint32), ("scheduler", ctypes.c_uint32),
+                ("native", ctypes.c_uint32)]
 
 
 class ProgramInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "n", "p", "n_in", "n_out", "n_stmt", "n_xor2", "n_mem", "nvar", "plain_xor2", "slots",
         "peak_open", "ring", "passes", "n_loads", "n_stores", "n_records", "n_ops", "n_words", "n_parts",
-        "n_row_parts", "n_pair_parts", "n_pass_parts", "scheduler", "n_stage_parts")] + [
+        "n_row_parts", "n_pair_parts", "n_pass_parts", "scheduler", "n_stage_parts", "native")] + [
         ("in_blocks", ctypes.POINTER(ctypes.c_int)), ("out_blocks", ctypes.POINTER(ctypes.c_int))]
 
 
@@ -119,6 +120,7 @@ def lib():
                                        ctypes.c_size_t, vp]
         L.ec_program_upload.argtypes = [vp]
         L.ec_program_upload_many.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.ec_program_native_source.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t)]
         L.ec_program_pool_stats.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_size_t)]
         L.ec_batch_reserve.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
@@ -141,7 +143,7 @@ def lib():
         for name in ("ec_matrix_cauchy", "ec_matrix_vandermonde", "ec_compile_slp", "ec_program_query",
                      "ec_encode", "ec_decode", "ec_program_export", "ec_program_export_greedy", "ec_program_bytecode", "ec_program_part_bytecode", "ec_batch_build", "ec_device_copy",
                      "ec_stripe_stream", "ec_batch_launch", "ec_batch_enqueue", "ec_batch_query", "ec_batch_create", "ec_batch_set",
-                     "ec_batch_run_noalloc", "ec_program_upload", "ec_program_upload_many", "ec_program_pool_stats",
+                     "ec_batch_run_noalloc", "ec_program_upload", "ec_program_upload_many", "ec_program_pool_stats", "ec_program_native_source",
                      "ec_server_create", "ec_server_run"):
             getattr(L, name).restype = st
         _lib = L
@@ -266,6 +268,13 @@ class Program:
         does it, synchronously)."""
         _check(lib().ec_program_upload(self._h), "ec_program_upload")
 
+    def native_source(self) -> str:
+        """Source of the program's native kernel (EcError if it has none)."""
+        src, n = ctypes.c_char_p(), ctypes.c_size_t()
+        _check(lib().ec_program_native_source(self._h, ctypes.byref(src), ctypes.byref(n)),
+               "ec_program_native_source")
+        return src.value[:n.value].decode()
+
     def bytecode(self):
         w = ctypes.POINTER(ctypes.c_uint32)()
         n = ctypes.c_size_t()
@@ -286,11 +295,12 @@ class Program:
 
 def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
                    compress: int = COMPRESS_XORREPAIR, block_strips: int = 0,
-                   prefetch: int | None = None, split: int = SPLIT_AUTO, scheduler: int = SCHED_PUSH) -> Program:
+                   prefetch: int | None = None, split: int = SPLIT_AUTO, scheduler: int = SCHED_PUSH,
+                   native: bool = False) -> Program:
     er = list(erased)
     er_arr = (ctypes.c_int * max(1, len(er)))(*er)
     opts = CompileOpts(level, slot_budget, compress, block_strips,
-                       DEFAULT_PREFETCH if prefetch is None else prefetch, split, scheduler)
+                       DEFAULT_PREFETCH if prefetch is None else prefetch, split, scheduler, int(native))
     h = ctypes.c_void_p()
     _check(lib().ec_compile_slp(n, p, _flat_gen(gen, n, p), er_arr, len(er), ctypes.byref(opts), ctypes.byref(h)),
            "ec_compile_slp")

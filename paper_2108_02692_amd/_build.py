@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libec.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp", "exec.hip", "staged.hip", "noalloc.hip", "ceiling.hip"]
+SOURCES = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp", "native.cpp", "exec.hip", "staged.hip", "noalloc.hip", "ceiling.hip"]
 # Packed FP32 instructions are disabled for all device code (none is used).
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
             if verbose and out:
                 print(out.decode(errors="replace"))
         tmp_lib = LIB + ".tmp%d" % os.getpid()
-        link = [HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp_lib] + objs
+        link = [HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp_lib] + objs + ["-lhiprtc"]
         r = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))

@@ -146,6 +146,25 @@ ec_status launch_staged(const ec_program *prog, ExecArgs &a, int n_cus, ec_strea
   return EC_OK;
 }
 
+// The whole program as its native kernel, one wave per tile: as many
+// workgroups as stay resident, each looping over tiles.
+ec_status launch_native(ec_program *prog, const ExecArgs &a, int n_cus, ec_stream stream) {
+  int dev = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
+  ec_status st = EC_OK;
+  hipFunction_t fn = prog->native_function(dev, &per_cu, &st);
+  if (!fn) return st;
+  ec::NativeArgs na{};
+  for (int b = 0; b < kMaxBlocks; ++b) na.blk[b] = a.blk[b];
+  na.sl = (uint32_t)a.strip_len;
+  na.n_tiles = a.n_tiles;
+  na.seg_shift = a.seg_shift;
+  na.seg_mask = a.seg_mask;
+  na.seg_tiles = a.seg_tiles;
+  const int grid = (int)std::min<uint64_t>(((uint64_t)a.n_tiles + 3) / 4, (uint64_t)n_cus * per_cu);
+  return ec::native_launch(fn, na, grid, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
+}
+
 ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *const *out, size_t block_bytes,
                  ec_stream stream) {
   if (!prog || !in || !out) return EC_ERR_ARG;
@@ -197,6 +216,8 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   if (off) {
     a.n_parts = (uint32_t)off->size();
     for (uint32_t q = 0; q < a.n_parts; ++q) a.part_off[q] = (*off)[q];
+  } else if (!prog->native_code.empty()) {
+    return launch_native(const_cast<ec_program *>(prog), a, n_cus, stream);
   }
   // As many workgroups as stay resident (4 waves each, one per SIMD, times
   // the waves per SIMD the slot budget allows), each looping over its work
@@ -243,10 +264,11 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
       if (erased[j] == erased[i]) return EC_ERR_ARG;
   }
   ec_compile_opts o{EC_LEVEL_CO_FU_SCHED, 0, EC_COMPRESS_XORREPAIR, 0, kDefaultPrefetch, EC_SPLIT_AUTO,
-                    EC_SCHED_PUSH};
+                    EC_SCHED_PUSH, 0};
   if (opts) o = *opts;
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.scheduler > EC_SCHED_GREEDY) return EC_ERR_UNSUPPORTED;
+  if (o.native > 1 || (o.native && o.split == EC_SPLIT_STAGED)) return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
   if (o.split > EC_SPLIT_STAGED) return EC_ERR_UNSUPPORTED;
@@ -504,6 +526,14 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
+  // The native kernel: the whole program's records as straight-line code.
+  if (o.native) {
+    std::string log;
+    prog->native_src = ec::native_source(prog->code.words, prog->slots, n_in + n_out);
+    const ec_status st = ec::native_compile(prog->native_src, &prog->native_code, &log);
+    if (st != EC_OK) return st;
+  }
+
   ec_program_info &info = prog->info;
   info.n = (uint32_t)n;
   info.p = (uint32_t)p;
@@ -530,6 +560,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_pass_parts = (uint32_t)prog->pass_parts.size();
   info.scheduler = o.scheduler;
   info.n_stage_parts = (uint32_t)prog->stage_parts.size();
+  info.native = prog->native_code.empty() ? 0u : 1u;
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -633,7 +664,20 @@ ec_status ec_stripe_stream(const uint8_t *const *in, int n_in, uint8_t *const *o
 ec_status ec_program_upload(ec_program *prog) {
   if (!prog) return EC_ERR_ARG;
   ec_status st = EC_OK;
-  return prog->device_words(&st) ? EC_OK : st;
+  if (!prog->device_words(&st)) return st;
+  if (!prog->native_code.empty()) {
+    int dev = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
+    if (!prog->native_function(dev, &per_cu, &st)) return st;
+  }
+  return EC_OK;
+}
+
+ec_status ec_program_native_source(const ec_program *prog, const char **src, size_t *len) {
+  if (!prog || !src || !len || prog->native_src.empty()) return EC_ERR_ARG;
+  *src = prog->native_src.c_str();
+  *len = prog->native_src.size();
+  return EC_OK;
 }
 
 ec_status ec_program_upload_many(ec_program *const *progs, int n) {
@@ -654,6 +698,8 @@ ec_status ec_program_upload_many(ec_program *const *progs, int n) {
   for (int i = 0; i < n; ++i) {
     ec_status st = EC_OK;
     if (!progs[i]->device_words(dev, &st)) return st;
+    int per_cu = 0;
+    if (!progs[i]->native_code.empty() && !progs[i]->native_function(dev, &per_cu, &st)) return st;
   }
   return EC_OK;
 }

@@ -1,0 +1,50 @@
+// native.hpp -- straight-line gfx950 kernels of compiled programs.
+//
+// A program's records (bytecode.hpp) are a fixed sequence of strip loads,
+// register XORs and strip stores per tile.  native_source() writes them out
+// as one inline-asm block of plain gfx950 instructions with every register
+// slot a fixed VGPR group, so a tile runs with no record dispatch, register
+// indexing or record-window loads: the interpreter's work without the
+// interpreter.  The source is compiled at run time with hiprtc (host only,
+// no device needed) and loaded per device on first use.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ec.h"
+
+namespace ec {
+
+// Arguments of a native kernel; the generated source declares the same
+// layout.  blk: the input blocks, then the output blocks; strips of sl
+// bytes; the tile order of tile_order.hpp.
+struct NativeArgs {
+  uint64_t blk[32];
+  uint32_t sl, n_tiles, seg_shift, seg_mask, seg_tiles;
+};
+
+// Name of the kernel in every generated source.
+constexpr const char *kNativeKernel = "ec_native_kernel";
+
+// The source of the native kernel for program words `words` (records for
+// `slots` register slots, reading and writing n_blocks blocks).  Strip
+// loads are non-temporal, stores device-scope (written through the L2).
+std::string native_source(const std::vector<uint32_t> &words, int slots, int n_blocks);
+
+// Compiles `src` for gfx950; the code object in *code.  EC_ERR_UNSUPPORTED
+// with the compiler's log in *log when it fails.
+ec_status native_compile(const std::string &src, std::vector<char> *code, std::string *log);
+
+// The kernel of `code` on device `dev` (the current device): loaded once
+// per device and code object, kept until the process ends.  *per_cu: the
+// workgroups of 256 lanes a compute unit holds at once.
+ec_status native_function(int dev, const std::vector<char> &code, hipFunction_t *fn, int *per_cu);
+
+// Launches `fn` on `grid` workgroups of 256 lanes; 0 on success.
+int native_launch(hipFunction_t fn, const NativeArgs &a, int grid, hipStream_t stream);
+
+}  // namespace ec

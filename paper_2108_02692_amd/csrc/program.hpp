@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/ec.h"
+#include "native.hpp"
 #include "program_pool.hpp"
 #include "push.hpp"
 #include "slp.hpp"
@@ -38,6 +39,9 @@ struct ec_program {
   std::vector<uint32_t> pair_part_off;   // word offset of each pair part in the image
   std::vector<uint32_t> pass_part_off;   // word offset of each pass part in the image
   std::vector<uint32_t> stage_part_off;  // word offset of each stage part in the image
+  std::string native_src;                // native kernel source (empty: none)
+  std::vector<char> native_code;         // its gfx950 code object
+  std::map<int, std::pair<hipFunction_t, int>> native_fn;  // device -> kernel, workgroups per CU
   int split = EC_SPLIT_AUTO;
   ec_program_info info{};
   std::mutex mu;
@@ -49,6 +53,22 @@ struct ec_program {
 
   ~ec_program() {
     for (auto &kv : dev_words) ec::pool_release(kv.first, kv.second);
+  }
+
+  // The native kernel on device `dev` (the current device), loaded on
+  // first use; null and *st set if it cannot be loaded.
+  hipFunction_t native_function(int dev, int *per_cu, ec_status *st) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = native_fn.find(dev);
+    if (it == native_fn.end()) {
+      hipFunction_t fn = nullptr;
+      int n = 0;
+      *st = ec::native_function(dev, native_code, &fn, &n);
+      if (*st != EC_OK) return nullptr;
+      it = native_fn.emplace(dev, std::make_pair(fn, n)).first;
+    }
+    *per_cu = it->second.second;
+    return it->second.first;
   }
 
   // Builds the whole-matrix CO/FU/SCHED stages of the program's level once.

@@ -93,6 +93,30 @@ def test_decode_64mib_every_byte(rs10_4_64mib, er):
 
 
 @pytest.mark.parametrize("level", [E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN])
+def test_native_64mib_every_byte(rs10_4_64mib, level):
+    """The native kernels of the benchmarked programs on the 64 MiB encode
+    and the {2,4,5,6} decode: every byte against the oracle."""
+    n, p, S, G, data, host, par = rs10_4_64mib
+    gen = gen_rows(n, p)
+    enc = E.ec_compile_slp(n, p, gen, level=level, native=True)
+    out = W.empty_blocks(p, S, fill=0xA5)
+    E.ec_encode(enc, data, out, S)
+    torch.cuda.synchronize()
+    for j in range(p):
+        first_diff(out[j].cpu().numpy(), par[j], "native 64 MiB encode level %d parity %d" % (level, j))
+    del out
+    er = [2, 4, 5, 6]
+    blocks = host + par
+    dev = list(data) + W.to_device(par)
+    dec = E.ec_compile_slp(n, p, gen, er, level=level, native=True)
+    rec = W.empty_blocks(len(er), S, fill=0xA5)
+    E.ec_decode(dec, [dev[i] for i in dec.in_blocks], rec, S)
+    torch.cuda.synchronize()
+    for j, e in enumerate(dec.out_blocks):
+        first_diff(rec[j].cpu().numpy(), blocks[e], "native 64 MiB decode %s block %d" % (er, e))
+
+
+@pytest.mark.parametrize("level", [E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN])
 def test_staged_64mib_every_byte(rs10_4_64mib, level):
     """The staged launch (tiles copied into LDS, one workgroup per tile) on
     the 64 MiB encode and the {2,4,5,6} decode: every byte against the

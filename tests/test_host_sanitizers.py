@@ -39,14 +39,14 @@ def run_driver(exe, cwd):
 
 @pytest.mark.slow
 def test_library_host_code_sanitized(tmp_path):
-    srcs = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp"]
+    srcs = ["gf.cpp", "slp.cpp", "push.cpp", "capi.cpp", "batch.cpp", "serve.cpp", "program_pool.cpp", "native.cpp"]
     inc = ["-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
     jobs = [(["g++"] + inc + SAN + ["-c", os.path.join(CSRC, s), "-o", s + ".o"]) for s in srcs]
     jobs.append(["g++"] + inc + SAN + ["-c", os.path.join(HERE, "sanitize", "lib_driver.cpp"), "-o", "drv.o"])
     with ThreadPoolExecutor(max_workers=6) as ex:
         list(ex.map(lambda c: run(c, tmp_path), jobs))
     run(["g++"] + SAN + ["-o", "lib_driver", "drv.o"] + [s + ".o" for s in srcs] +
-        ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"], tmp_path)
+        ["-L/opt/rocm/lib", "-lamdhip64", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"], tmp_path)
     out = run_driver(str(tmp_path / "lib_driver"), tmp_path)
     assert "0 check failures" in out
 
