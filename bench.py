@@ -58,6 +58,12 @@ def parse():
                          "drain figures are their medians (every run's in 'runs')")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--decode-all-slots", type=int, default=44, help="slot budget of the every-erasure-set decode")
+    ap.add_argument("--exec", choices=["native", "interp"], default="native",
+                    help="executor of the headline programs: their native kernels, or the record interpreter")
+    ap.add_argument("--rotate-in", type=int, default=2,
+                    help="input block sets the headline launches rotate over (1 = the same every launch)")
+    ap.add_argument("--rotate-out", type=int, default=4,
+                    help="output block sets the headline launches rotate over (1 = the same every launch)")
     ap.add_argument("--sweep", action="store_true",
                     help="time every (level, slot budget) pair on the workload and print one line each")
     ap.add_argument("--sweep-prefetch", action="store_true", help="with --sweep: also vary the prefetch distance")
@@ -114,6 +120,21 @@ def time_launches(fn, steps, warmup, stream, prewarm_ms=None):
     return start.elapsed_time(end) / steps
 
 
+def rotating(launch, ins_sets, outs_sets):
+    """A launch function that takes the next (input set, output set) pair on
+    every call: call i uses input set i % R_in and output set i % R_out, so
+    that no launch writes the lines the launch before it wrote (a launch
+    that rewrites them finds them in the memory-side cache, and stores that
+    allocate there then look up to 13% faster than HBM allows)."""
+    k = [0]
+
+    def f():
+        i = k[0]
+        k[0] += 1
+        launch(ins_sets[i % len(ins_sets)], outs_sets[i % len(outs_sets)])
+    return f
+
+
 def code_sha(*paths):
     """sha256 of C++/HIP sources with comments and blank lines removed, so
     that an edit of comments alone keeps a measurement valid."""
@@ -143,11 +164,16 @@ def program_sha(prog):
     return hashlib.sha256(struct.pack("<%dI" % len(w), *w)).hexdigest()
 
 
-def measured_traffic(prog):
+def measured_traffic(prog, native=False):
     """HBM bytes per launch from the committed byte-counter profile of this
-    workload, if it was taken on this executor and this program (else None)."""
-    exec_sha = executor_sha()
-    psha = program_sha(prog)
+    workload, if it was taken on this executor and this program (else None).
+    A native kernel is identified by its source, which holds both."""
+    if native:
+        exec_sha = "native"
+        psha = hashlib.sha256(prog.native_source().encode()).hexdigest()
+    else:
+        exec_sha = executor_sha()
+        psha = program_sha(prog)
     if not os.path.isdir(PROFILES):
         return None
     for name in sorted(os.listdir(PROFILES)):
@@ -197,75 +223,78 @@ def main():
     n, p = 10, 4
     S = args.block_mib << 20
     gen = E.ec_matrix_cauchy(n, p)
-    data = W.device_blocks(n, S, seed=2021)
-    parity = W.empty_blocks(p, S)
+    # Launch i reads input set i % R_in and writes output set i % R_out, so
+    # that no launch rewrites the output lines of the one before (the
+    # memory-side cache could still hold them) or reads the inputs its
+    # predecessor read.
+    sets_in = [W.device_blocks(n, S, seed=2021 + r) for r in range(max(1, args.rotate_in))]
+    sets_out = [W.empty_blocks(p, S) for _ in range(max(1, args.rotate_out))]
+    data, parity = sets_in[0], sets_out[0]
     torch.cuda.synchronize()
     in_bytes = n * S
     moved = (n + p) * S  # algorithmic bytes per launch: read n blocks, write p blocks
+    native = args.exec == "native"
 
-    def measure(prog, ins, outs, decode=False):
-        f = (lambda: E.ec_decode(prog, ins, outs, S, stream)) if decode else \
-            (lambda: E.ec_encode(prog, ins, outs, S, stream))
-        return time_launches(f, args.steps, args.warmup, stream)
+    def measure(prog, ins_sets, outs_sets, decode=False, prewarm_ms=None):
+        run = E.ec_decode if decode else E.ec_encode
+        return time_launches(rotating(lambda i, o: run(prog, i, o, S, stream), ins_sets, outs_sets), args.steps,
+                             args.warmup, stream, prewarm_ms=prewarm_ms)
 
     t0 = time.time()
-    comp = E.ec_compile_slp(n, p, gen, level=E.LEVEL_CO_FU_SCHED, slot_budget=args.slots)
+    comp = E.ec_compile_slp(n, p, gen, level=E.LEVEL_CO_FU_SCHED, slot_budget=args.slots, native=native)
     compile_ms = (time.time() - t0) * 1e3
-    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots)
-    log("compiled (compressed %.0f ms, %d slots; plain %d slots)" % (compile_ms, comp.info["slots"],
-                                                                     plain.info["slots"]))
-    if args.sweep:
-        for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
-            for K in (32, 36, 38, 40, 44, 48):
-                for dist in ((0, 4, 12) if args.sweep_prefetch else (0,)):
-                    pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K, prefetch=dist)
-                    ms = measure(pr, data, parity)
-                    print(json.dumps({"sweep": True, "level": level, "slots": K, "prefetch": dist, "ms": ms,
-                                      "GB_s": in_bytes / ms / 1e6, "hbm_frac": moved / ms / 1e6 / HBM_PEAK_GBS,
-                                      "n_xor2": pr.info["n_xor2"], "ops": pr.info["n_ops"],
-                                      "records": pr.info["n_records"], "ring": pr.info["ring"],
-                                      "open": pr.info["peak_open"]}), flush=True)
-        return
-
-    if args.only == "schedulers":
-        print(json.dumps({"schedulers": bench_schedulers(args, stream, gen, data, parity)}), flush=True)
-        return
-    if args.only == "staged":
-        print(json.dumps({"staged": bench_staged(args, stream, gen, data, parity)}), flush=True)
-        return
+    plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots, native=native)
+    log("compiled (compressed %.0f ms, %d slots; plain %d slots; %s)" % (
+        compile_ms, comp.info["slots"], plain.info["slots"], args.exec))
     res = {}
     if args.only in ("all", "compressed"):
-        res["compressed"] = measure(comp, data, parity)
+        res["compressed"] = measure(comp, sets_in, sets_out)
     if args.only in ("all", "plain"):
-        res["plain"] = measure(plain, data, parity)
+        res["plain"] = measure(plain, sets_in, sets_out)
     log("encode timed: %s" % res)
     cold = None
     if args.only == "all":
         # the same launches timed after 0.2 s idle with no copies before the
         # warm-up launches: what a run starting from an idle GPU sees
         time.sleep(0.2)
-        cold = time_launches(lambda: E.ec_encode(comp, data, parity, S, stream), args.steps, args.warmup, stream,
-                             prewarm_ms=0)
+        cold = measure(comp, sets_in, sets_out, prewarm_ms=0)
     extra = {}
+    if args.only == "all" and native:
+        # the record interpreter on the same programs and buffers
+        icomp = E.ec_compile_slp(n, p, gen, level=E.LEVEL_CO_FU_SCHED, slot_budget=args.slots)
+        iplain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots)
+        ic, ip = measure(icomp, sets_in, sets_out), measure(iplain, sets_in, sets_out)
+        extra["interpreter"] = {
+            "compressed": {"ms": ic, "hbm_frac": moved / ic / 1e6 / HBM_PEAK_GBS, "slots": icomp.info["slots"]},
+            "plain": {"ms": ip, "hbm_frac": moved / ip / 1e6 / HBM_PEAK_GBS, "slots": iplain.info["slots"]},
+            "kernel": "slp_exec_kernel_%d" % icomp.info["slots"]}
+        log("interpreter: compressed %.4f ms, plain %.4f ms" % (ic, ip))
     if args.only in ("all", "decode"):
-        # decode of 4 lost data blocks (the paper's decode example erases 4)
+        # decode of 4 lost data blocks (the paper's decode example erases 4):
+        # the survivors of input set r are its data blocks and their parity
         er = [2, 4, 5, 6]
-        dprog = E.ec_compile_slp(n, p, gen, er)
-        blocks = data + parity
-        E.ec_encode(comp, data, parity, S, stream)
-        surv = [blocks[i] for i in dprog.in_blocks]
-        rec = W.empty_blocks(len(er), S)
-        ms_dec = measure(dprog, surv, rec, decode=True)
+        dprog = E.ec_compile_slp(n, p, gen, er, native=native)
+        surv_sets = []
+        for d in sets_in:
+            par_d = W.empty_blocks(p, S)
+            E.ec_encode(comp, d, par_d, S, stream)
+            blocks = d + par_d
+            surv_sets.append([blocks[i] for i in dprog.in_blocks])
+        rec_sets = [W.empty_blocks(len(er), S) for _ in sets_out]
+        ms_dec = measure(dprog, surv_sets, rec_sets, decode=True)
         torch.cuda.synchronize()
-        for j, e in enumerate(er):
-            if not torch.equal(rec[j], blocks[e]):
-                raise SystemExit("bench.py: decode self-check failed for block %d" % e)
+        for r, d in enumerate(sets_in):
+            E.ec_decode(dprog, surv_sets[r], rec_sets[0], S, stream)
+            torch.cuda.synchronize()
+            for j, e in enumerate(er):
+                if not torch.equal(rec_sets[0][j], d[e]):
+                    raise SystemExit("bench.py: decode self-check failed for block %d" % e)
         dmoved = (n + len(er)) * S
         extra["decode"] = {"erased": er, "ms": ms_dec, "GB_s": in_bytes / ms_dec / 1e6,
                            "hbm_frac": dmoved / ms_dec / 1e6 / HBM_PEAK_GBS, "slots": dprog.info["slots"],
                            "n_xor2": dprog.info["n_xor2"], "plain_xor2": dprog.info["plain_xor2"],
-                           "ops_per_tile": dprog.info["n_ops"]}
-        del rec
+                           "ops_per_tile": dprog.info["n_ops"], "executor": args.exec}
+        del rec_sets, surv_sets
     if args.only in ("all", "copy") or args.calib:
         # plain device copy of the same number of bytes (read + write = moved)
         src = torch.empty(moved // 2, dtype=torch.uint8, device="cuda")
@@ -281,12 +310,13 @@ def main():
     if args.only in ("all", "copy"):
         # the encode's own data movement (10 blocks read, 4 written, same
         # tile order) with no program: the ceiling for this access pattern
-        ms_stream = time_launches(lambda: E.ec_stripe_stream(data, parity, S, stream), args.steps, args.warmup,
-                                  stream)
+        ms_stream = time_launches(rotating(lambda i, o: E.ec_stripe_stream(i, o, S, stream), sets_in, sets_out),
+                                  args.steps, args.warmup, stream)
         extra["stripe_ceiling"] = {"ms": ms_stream, "GB_s": moved / ms_stream / 1e6,
                                    "hbm_frac": moved / ms_stream / 1e6 / HBM_PEAK_GBS,
                                    "what": "ec_stripe_stream: 10 x %d MiB read, 4 x %d MiB written, executor tile "
-                                           "order, no program" % (args.block_mib, args.block_mib)}
+                                           "order and cache policies, no program, same buffer rotation"
+                                           % (args.block_mib, args.block_mib)}
     if args.only == "copy":
         print(json.dumps(extra), flush=True)
         return
@@ -321,6 +351,8 @@ def main():
             "workload": "RS(10,4) encode, Cauchy GF(2^8)/0x11D, 10 x %d MiB data -> 4 x %d MiB parity"
                         % (args.block_mib, args.block_mib),
             "program": "compressed+fused+scheduled" if head == "compressed" else "plain bitmatrix",
+            "executor": "native kernel" if native else "record interpreter",
+            "buffers": "%d input sets x %d output sets, rotating" % (len(sets_in), len(sets_out)),
             "block_bytes": S,
             "slots": info["slots"],
             "n_xor2": info["n_xor2"],
@@ -330,8 +362,8 @@ def main():
             "compile_ms": compile_ms,
         },
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(hprog),
-                     "kernel": "slp_exec_kernel_%d" % info["slots"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(hprog, native),
+                     "kernel": "ec_native_kernel" if native else "slp_exec_kernel_%d" % info["slots"]},
     }
     out["prewarm"] = {"ms": PREWARM_MS, "kernel": "ec_device_copy, 256 MiB per launch",
                       "when": "before every timed run's warm-up launches"}
@@ -350,7 +382,7 @@ def main():
     if "stripe_ceiling" in out:
         out["roofline"]["frac_of_stripe_ceiling"] = achieved / out["stripe_ceiling"]["GB_s"]
     if args.only == "all":
-        del data, parity
+        del data, parity, sets_in, sets_out
         torch.cuda.empty_cache()
         log("decode of every erasure set ...")
         out["decode_all"] = bench_decode_all(args, stream)
@@ -464,50 +496,64 @@ def bench_codecs(args, stream):
     """RS(d,4), RS(d,3) and RS(d,2) for d = 8, 9, 10 (the codecs of the
     paper's throughput comparison, with Cauchy matrices): encode, and decode
     of the worst set of p lost data blocks, each compressed and plain, on
-    d blocks of 64 MiB resident in HBM."""
+    d blocks of 64 MiB resident in HBM, with the headline's executor and
+    buffer rotation (the outputs rotate over --rotate-out sets; the
+    programs are compiled on host threads first)."""
+    from concurrent.futures import ThreadPoolExecutor
     import torch
     import paper_2108_02692_amd as E
     from paper_2108_02692_amd import workloads as W
     S = args.block_mib << 20
+    native = args.exec == "native"
+    codecs = [(n, p) for p in (4, 3, 2) for n in (8, 9, 10)]
+    gens = {c: E.ec_matrix_cauchy(*c) for c in codecs}
+    ers = {c: worst_erasures(c[0], c[1], gens[c]) for c in codecs}
+    jobs = [(c, level, er) for c in codecs for level in (E.LEVEL_CO_FU_SCHED, E.LEVEL_PLAIN) for er in ((), tuple(ers[c]))]
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        progs = dict(zip(jobs, ex.map(lambda j: E.ec_compile_slp(j[0][0], j[0][1], gens[j[0]], list(j[2]),
+                                                                 level=j[1], native=native), jobs)))
     rows = []
-    for p in (4, 3, 2):
-        for n in (8, 9, 10):
-            gen = E.ec_matrix_cauchy(n, p)
-            er = worst_erasures(n, p, gen)
-            data = W.device_blocks(n, S, seed=100 + 10 * n + p)
-            parity = W.empty_blocks(p, S)
-            rec = W.empty_blocks(p, S)
-            row = {"codec": "RS(%d,%d)" % (n, p), "erased": er}
-            ref = None
-            for level, tag in ((E.LEVEL_CO_FU_SCHED, "comp"), (E.LEVEL_PLAIN, "plain")):
-                enc = E.ec_compile_slp(n, p, gen, level=level)
-                ms = time_launches(lambda: E.ec_encode(enc, data, parity, S, stream), args.steps, args.warmup,
-                                   stream)
-                torch.cuda.synchronize()
-                if ref is None:
-                    ref = [t.clone() for t in parity]
-                elif not all(torch.equal(a, b) for a, b in zip(ref, parity)):
-                    raise SystemExit("bench.py: compressed and plain parity differ for %s" % row["codec"])
-                row["enc_" + tag] = {"ms": ms, "GB_s": n * S / ms / 1e6,
-                                     "hbm_frac": (n + p) * S / ms / 1e6 / HBM_PEAK_GBS,
-                                     "n_xor2": enc.info["n_xor2"], "slots": enc.info["slots"]}
-                dec = E.ec_compile_slp(n, p, gen, er, level=level)
-                blocks = data + ref
-                surv = [blocks[i] for i in dec.in_blocks]
-                ms = time_launches(lambda: E.ec_decode(dec, surv, rec, S, stream), args.steps, args.warmup,
-                                   stream)
-                torch.cuda.synchronize()
-                for j, e in enumerate(dec.out_blocks):
-                    if not torch.equal(rec[j], blocks[e]):
-                        raise SystemExit("bench.py: %s decode self-check failed" % row["codec"])
-                row["dec_" + tag] = {"ms": ms, "GB_s": n * S / ms / 1e6,
-                                     "hbm_frac": (n + len(er)) * S / ms / 1e6 / HBM_PEAK_GBS,
-                                     "n_xor2": dec.info["n_xor2"], "slots": dec.info["slots"]}
-            log("%s: enc %.1f GB/s dec %.1f GB/s" % (row["codec"], row["enc_comp"]["GB_s"],
-                                                      row["dec_comp"]["GB_s"]))
-            rows.append(row)
-            del data, parity, rec, ref, blocks, surv
-            torch.cuda.empty_cache()
+    for (n, p) in codecs:
+        gen = gens[(n, p)]
+        er = ers[(n, p)]
+        data = W.device_blocks(n, S, seed=100 + 10 * n + p)
+        par_sets = [W.empty_blocks(p, S) for _ in range(max(1, args.rotate_out))]
+        parity = par_sets[0]
+        rec_sets = [W.empty_blocks(p, S) for _ in range(max(1, args.rotate_out))]
+        rec = rec_sets[0]
+        row = {"codec": "RS(%d,%d)" % (n, p), "erased": er}
+        ref = None
+        for level, tag in ((E.LEVEL_CO_FU_SCHED, "comp"), (E.LEVEL_PLAIN, "plain")):
+            enc = progs[((n, p), level, ())]
+            ms = time_launches(rotating(lambda i, o: E.ec_encode(enc, i, o, S, stream), [data], par_sets),
+                               args.steps, args.warmup, stream)
+            E.ec_encode(enc, data, parity, S, stream)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = [t.clone() for t in parity]
+            elif not all(torch.equal(a, b) for a, b in zip(ref, parity)):
+                raise SystemExit("bench.py: compressed and plain parity differ for %s" % row["codec"])
+            row["enc_" + tag] = {"ms": ms, "GB_s": n * S / ms / 1e6,
+                                 "hbm_frac": (n + p) * S / ms / 1e6 / HBM_PEAK_GBS,
+                                 "n_xor2": enc.info["n_xor2"], "slots": enc.info["slots"]}
+            dec = progs[((n, p), level, tuple(er))]
+            blocks = data + ref
+            surv = [blocks[i] for i in dec.in_blocks]
+            ms = time_launches(rotating(lambda i, o: E.ec_decode(dec, i, o, S, stream), [surv], rec_sets),
+                               args.steps, args.warmup, stream)
+            E.ec_decode(dec, surv, rec, S, stream)
+            torch.cuda.synchronize()
+            for j, e in enumerate(dec.out_blocks):
+                if not torch.equal(rec[j], blocks[e]):
+                    raise SystemExit("bench.py: %s decode self-check failed" % row["codec"])
+            row["dec_" + tag] = {"ms": ms, "GB_s": n * S / ms / 1e6,
+                                 "hbm_frac": (n + len(er)) * S / ms / 1e6 / HBM_PEAK_GBS,
+                                 "n_xor2": dec.info["n_xor2"], "slots": dec.info["slots"]}
+        log("%s: enc %.1f GB/s dec %.1f GB/s" % (row["codec"], row["enc_comp"]["GB_s"],
+                                                  row["dec_comp"]["GB_s"]))
+        rows.append(row)
+        del data, parity, rec, ref, blocks, surv, par_sets, rec_sets
+        torch.cuda.empty_cache()
     return rows
 
 

@@ -118,7 +118,7 @@ typedef struct {
  * per tile (no row split: ec_encode / ec_decode of long stripes), then runs
  * that kernel instead of the interpreter: the same loads, XORs and stores
  * in the same order, with no record dispatch, register indexing or record
- * loads, so about a third of the instructions, and device-scope stores.
+ * loads: a fraction of the instructions.
  * Split launches and batches keep the interpreter.  The kernel is loaded on
  * a device at the program's upload or first launch there and stays loaded
  * until the process ends (identical kernels are loaded once).  Not with

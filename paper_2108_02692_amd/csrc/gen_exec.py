@@ -89,12 +89,12 @@ def handler(K, kind, W, O, run_base, h_other, lds=False):
           "s_addc_u32 s81, s93, 0",
           "s_swappc_b64 s[78:79], s[80:81]"]
     # strips are streamed once: loads and stores are non-temporal (measured:
-    # 0.58 -> 0.69 of peak HBM bandwidth on the 64 MiB-block encode).  The
-    # launch's data movement alone runs faster with device-scope stores
-    # (sc1, 0.81 against 0.73 of peak), but the interpreter does not: its
-    # own issue rate holds it near 0.72, and the slower store completions
-    # then cost it (64 MiB encode 0.168 against 0.163 ms; a batch of 1 MiB
-    # decodes 4.05 against 3.49 ms)
+    # 0.58 -> 0.69 of peak HBM bandwidth on the 64 MiB-block encode).
+    # Device-scope (sc1) or plain stores are slower here (64 MiB encode
+    # 0.168 and 0.165 against 0.163 ms; a batch of 1 MiB decodes 4.05
+    # against 3.49 ms).  They look faster only when a launch rewrites the
+    # lines the launch before it wrote, which the memory-side cache then
+    # absorbs; with outputs that change every launch they are no faster.
     store = ["global_store_dwordx4 %[voff], v[0:3], s[72:73] nt",
              # one wait state before a VALU may overwrite the store's data
              "s_nop 1"]

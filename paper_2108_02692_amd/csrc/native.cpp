@@ -44,7 +44,7 @@ void line(std::string &s, const std::string &ins) { s += "        \"" + ins + "\
 //   WAIT    s_waitcnt vmcnt(n)
 //   PULL    acc = slot (4 v_mov)
 //   LD      global_load_dwordx4 slot, strip offset, block base, non-temporal
-//   STORE   global_store_dwordx4 acc, device scope, then one wait state
+//   STORE   global_store_dwordx4 acc, non-temporal, then one wait state
 //           before the next VALU may overwrite acc
 //   run     slot ^= acc (4 v_xor) per operand
 // PREFETCH records are hints and are left out (each wait then counts one
@@ -65,7 +65,7 @@ std::string body(const std::vector<uint32_t> &w) {
     if (kind == bc::INPUT_LD || kind == bc::LOAD)
       line(s, fmt("global_load_dwordx4 v[%d:%d], %%[o%d], %%[b%d] nt", 4 + 4 * ld, 7 + 4 * ld, j, blk));
     if (kind == bc::STORE) {
-      line(s, fmt("global_store_dwordx4 %%[o%d], v[0:3], %%[b%d] sc1", j, blk));
+      line(s, fmt("global_store_dwordx4 %%[o%d], v[0:3], %%[b%d] nt", j, blk));
       line(s, "s_nop 1");
     }
     for (int i = 0; i < n; ++i) {

@@ -32,7 +32,7 @@ constexpr const char *kNativeKernel = "ec_native_kernel";
 
 // The source of the native kernel for program words `words` (records for
 // `slots` register slots, reading and writing n_blocks blocks).  Strip
-// loads are non-temporal, stores device-scope (written through the L2).
+// loads and stores are non-temporal, as the interpreter's.
 std::string native_source(const std::vector<uint32_t> &words, int slots, int n_blocks);
 
 // Compiles `src` for gfx950; the code object in *code.  EC_ERR_UNSUPPORTED

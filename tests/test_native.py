@@ -62,7 +62,7 @@ def run_symbolic(body, n_in, tiles=2):
                 j = int(re.match(r"%\[o(\d)\]", args[0]).group(1))
                 assert args[1] == "v[0:3]"
                 b, pol = re.match(r"%\[b(\d+)\] (\w+)", args[2]).groups()
-                assert pol == "sc1" and int(b) >= n_in
+                assert pol == "nt" and int(b) >= n_in
                 assert reg.get(0, 0) == reg.get(1, 0) == reg.get(2, 0) == reg.get(3, 0)
                 key = (int(b) - n_in, j)
                 assert key not in stores, "strip stored twice"
