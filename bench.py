@@ -246,6 +246,27 @@ def main():
     plain = E.ec_compile_slp(n, p, gen, level=E.LEVEL_PLAIN, slot_budget=args.plain_slots, native=native)
     log("compiled (compressed %.0f ms, %d slots; plain %d slots; %s)" % (
         compile_ms, comp.info["slots"], plain.info["slots"], args.exec))
+    if args.sweep:
+        for level in (E.LEVEL_PLAIN, E.LEVEL_CO_FU_SCHED):
+            for K in (32, 36, 38, 40, 44, 48):
+                for dist in ((0, 4, 12) if args.sweep_prefetch else (0,)):
+                    pr = E.ec_compile_slp(n, p, gen, level=level, slot_budget=K, prefetch=dist,
+                                          native=native and dist == 0)
+                    ms = measure(pr, sets_in, sets_out)
+                    print(json.dumps({"sweep": True, "level": level, "slots": K, "prefetch": dist,
+                                      "native": bool(pr.info["native"]), "ms": ms,
+                                      "GB_s": in_bytes / ms / 1e6, "hbm_frac": moved / ms / 1e6 / HBM_PEAK_GBS,
+                                      "n_xor2": pr.info["n_xor2"], "ops": pr.info["n_ops"],
+                                      "records": pr.info["n_records"], "ring": pr.info["ring"],
+                                      "open": pr.info["peak_open"]}), flush=True)
+        return
+
+    if args.only == "schedulers":
+        print(json.dumps({"schedulers": bench_schedulers(args, stream, gen, data, parity)}), flush=True)
+        return
+    if args.only == "staged":
+        print(json.dumps({"staged": bench_staged(args, stream, gen, data, parity)}), flush=True)
+        return
     res = {}
     if args.only in ("all", "compressed"):
         res["compressed"] = measure(comp, sets_in, sets_out)
@@ -411,10 +432,11 @@ def main():
 
 def bench_schedulers(args, stream, gen, data, parity):
     """The two strip orders (EC_SCHED_PUSH, EC_SCHED_GREEDY) at the
-    compressed and the plain level, on the RS(10,4) encode of 10 x 64 MiB
-    (the data above), the decode of {2, 4, 5, 6} at that size, and the
-    encode of 10 x 1 MiB, through the single-stripe autotuner (every
-    candidate timed, the fastest reported as its choice)."""
+    compressed and the plain level, run by the interpreter and (with --exec
+    native) as native kernels, on the RS(10,4) encode of 10 x 64 MiB (the
+    data above), the decode of {2, 4, 5, 6} at that size, and the encode of
+    10 x 1 MiB, through the single-stripe autotuner (every candidate timed,
+    the fastest reported as its choice)."""
     import paper_2108_02692_amd as E
     from paper_2108_02692_amd import autotune
     from paper_2108_02692_amd import workloads as W
@@ -432,14 +454,19 @@ def bench_schedulers(args, stream, gen, data, parity):
     cases = (("RS(10,4) encode 10 x 64 MiB", (), data, parity, S),
              ("RS(10,4) decode {2,4,5,6} 10 x 64 MiB", (2, 4, 5, 6), [blocks[i] for i in dec.in_blocks], rec, S),
              ("RS(10,4) encode 10 x 1 MiB", (), small, small_par, 1 << 20))
+    cands = autotune.STRIPE_CANDIDATES_NATIVE if args.exec == "native" else autotune.STRIPE_CANDIDATES
     for what, er, ins, outs, bb in cases:
-        best, table = autotune.tune_stripe(n, p, gen, er, ins, outs, bb, stream, retune=True, time_fn=timer)
+        best, table = autotune.tune_stripe(n, p, gen, er, ins, outs, bb, stream, candidates=cands, retune=True,
+                                           time_fn=timer)
         moved = (n + len(outs)) * bb
-        rows.append({"workload": what, "choice": {"level": best["level"], "scheduler": name[best["scheduler"]]},
+        rows.append({"workload": what, "choice": {"level": best["level"], "scheduler": name[best["scheduler"]],
+                                                  "slots": best["slots"], "native": best["native"]},
                      "candidates": [{"level": r["level"], "scheduler": name[r["scheduler"]], "slots": r["slots"],
-                                     "ms": r["ms"], "hbm_frac": moved / r["ms"] / 1e6 / HBM_PEAK_GBS,
+                                     "native": r["native"], "ms": r["ms"],
+                                     "hbm_frac": moved / r["ms"] / 1e6 / HBM_PEAK_GBS,
                                      "records": r["records"], "ops": r["ops"]} for r in table]})
-        log("%s: %s" % (what, ", ".join("%s/%s %.4f ms" % (r["level"], name[r["scheduler"]], r["ms"])
+        log("%s: %s" % (what, ", ".join("%s/%s%s %.4f ms" % (r["level"], name[r["scheduler"]],
+                                                             "/native" if r["native"] else "", r["ms"])
                                          for r in table)))
     return rows
 

@@ -24,10 +24,17 @@ DEFAULT_CANDIDATES = (
     (LEVEL_CO_FU_SCHED, 38, 1024, SCHED_GREEDY), (LEVEL_CO_FU_SCHED, 44, 1024, SCHED_GREEDY),
     (LEVEL_PLAIN, 38, 1024, SCHED_GREEDY),
 )
-# (level, slot budget (0 = the compiler's rule), strip scheduler) for one stripe
+# (level, slot budget (0 = the compiler's rule), strip scheduler[, native
+# kernel]) for one stripe
 STRIPE_CANDIDATES = (
     (LEVEL_CO_FU_SCHED, 0, SCHED_PUSH), (LEVEL_CO_FU_SCHED, 0, SCHED_GREEDY),
     (LEVEL_PLAIN, 0, SCHED_PUSH), (LEVEL_PLAIN, 0, SCHED_GREEDY),
+)
+# the same with the programs' native kernels beside the interpreter (each
+# native candidate costs a run-time compile of about a second)
+STRIPE_CANDIDATES_NATIVE = STRIPE_CANDIDATES + (
+    (LEVEL_CO_FU_SCHED, 0, SCHED_PUSH, True), (LEVEL_CO_FU_SCHED, 0, SCHED_GREEDY, True),
+    (LEVEL_PLAIN, 0, SCHED_PUSH, True), (LEVEL_PLAIN, 36, SCHED_PUSH, True),
 )
 CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
@@ -104,24 +111,27 @@ def _time_launches(fn, stream, steps=20, warmup=5):
 
 def tune_stripe(n, p, gen, erased, inputs, outputs, block_bytes, stream, candidates=STRIPE_CANDIDATES,
                 path=CACHE_PATH, retune=False, time_fn=None):
-    """One stripe's launch: times each (level, slot budget, scheduler) on the
-    caller's buffers (``inputs`` in the program's in_blocks order, which is
-    the same for every candidate) and returns (best dict, table of all
-    timings), the choice cached under the codec, erasure set and block
-    size.  ``time_fn(launch)`` gives the ms per launch (default: 5 untimed
-    launches, then the mean of 20)."""
+    """One stripe's launch: times each (level, slot budget, scheduler[,
+    native]) on the caller's buffers (``inputs`` in the program's in_blocks
+    order, which is the same for every candidate) and returns (best dict,
+    table of all timings), the choice cached under the codec, erasure set
+    and block size.  ``time_fn(launch)`` gives the ms per launch (default:
+    5 untimed launches, then the mean of 20)."""
     key = "stripe-RS(%d,%d)-%s-%d" % (n, p, ",".join(map(str, erased)) or "enc", block_bytes)
     table = _load(path)
     if key in table and not retune:
         return table[key], None
     time_fn = time_fn or (lambda f: _time_launches(f, stream))
     results = []
-    for level, slots, sched in candidates:
-        prog = ec_compile_slp(n, p, gen, list(erased), level=level, slot_budget=slots, scheduler=sched)
+    for cand in candidates:
+        level, slots, sched = cand[:3]
+        native = bool(cand[3]) if len(cand) > 3 else False
+        prog = ec_compile_slp(n, p, gen, list(erased), level=level, slot_budget=slots, scheduler=sched,
+                              native=native)
         run = ec_decode if erased else ec_encode
         ms = time_fn(lambda: run(prog, inputs, outputs, block_bytes, stream))
-        results.append({"level": level, "slots": prog.info["slots"], "scheduler": sched, "ms": ms,
-                        "records": prog.info["n_records"], "ops": prog.info["n_ops"]})
+        results.append({"level": level, "slots": prog.info["slots"], "scheduler": sched, "native": native,
+                        "ms": ms, "records": prog.info["n_records"], "ops": prog.info["n_ops"]})
     best = min(results, key=lambda r: r["ms"])
     table[key] = best
     _store(path, table)
