@@ -106,10 +106,16 @@ typedef struct {
   uint32_t split;        /* EC_SPLIT_*: whether a launch may run the output rows of one
                             tile on different waves (see ec_program_info.n_parts) */
   uint32_t scheduler;    /* EC_SCHED_*; default EC_SCHED_PUSH */
-  uint32_t native;       /* 1: also compile the program into a native kernel (below); default 0 */
+  uint32_t native;       /* EC_NATIVE_* bits: native kernels to compile (below); default 0 */
 } ec_compile_opts;
 
-/* Native kernels (ec_compile_opts.native = 1).  The program's records, a
+/* Native kernels to compile (ec_compile_opts.native, ec_program_info.native). */
+enum {
+  EC_NATIVE_WHOLE = 1, /* the whole program: launches with no row split */
+  EC_NATIVE_PAIRS = 2  /* the pair parts (when the program has them): launches that split into pairs */
+};
+
+/* Native kernels (ec_compile_opts.native).  The program's records, a
  * fixed sequence of strip loads, register XORs and strip stores per tile,
  * are also written out as straight-line gfx950 code with every register
  * slot a fixed register group, and compiled at ec_compile_slp time with
@@ -118,8 +124,15 @@ typedef struct {
  * per tile (no row split: ec_encode / ec_decode of long stripes), then runs
  * that kernel instead of the interpreter: the same loads, XORs and stores
  * in the same order, with no record dispatch, register indexing or record
- * loads: a fraction of the instructions.
- * Split launches and batches keep the interpreter.  The kernel is loaded on
+ * loads: a fraction of the instructions.  EC_NATIVE_PAIRS compiles the
+ * pair parts the same way into one kernel (work item k runs pair part
+ * k % n_pair_parts of tile k / n_pair_parts), which then runs every launch
+ * that splits into pair parts; it takes about 5 s to compile for RS(10,4).
+ * With native kernels EC_SPLIT_AUTO takes the native pair parts while
+ * there is at most one wave per SIMD (up to 512 KiB blocks for RS(10,4)),
+ * else the native whole program, and only without them the interpreter's
+ * rule (EC_SPLIT_AUTO below).  Other split launches and batches keep the
+ * interpreter.  The kernel is loaded on
  * a device at the program's upload or first launch there and stays loaded
  * until the process ends (identical kernels are loaded once).  Not with
  * EC_SPLIT_STAGED (EC_ERR_UNSUPPORTED); EC_ERR_UNSUPPORTED also if the
@@ -204,7 +217,7 @@ typedef struct {
   uint32_t n_pass_parts; /* pass parts (0: none; the program needs one pass) */
   uint32_t scheduler;   /* EC_SCHED_* the strip order was made with */
   uint32_t n_stage_parts; /* stage parts (EC_SPLIT_STAGED only; 0: none) */
-  uint32_t native;      /* 1: the program has a native kernel */
+  uint32_t native;      /* EC_NATIVE_* bits of the native kernels the program has */
   const int *in_blocks;  /* n_in block indices (0..n+p-1) read, in argument order */
   const int *out_blocks; /* n_out block indices written, in argument order */
 } ec_program_info;
@@ -284,10 +297,11 @@ ec_status ec_program_upload(ec_program *prog);
  * on an error the programs before the failing one stay uploaded. */
 ec_status ec_program_upload_many(ec_program *const *progs, int n);
 
-/* The source of the program's native kernel (host copy, valid until
- * ec_program_free; *len without a terminating zero, which follows it).
- * EC_ERR_ARG if the program has none. */
-ec_status ec_program_native_source(const ec_program *prog, const char **src, size_t *len);
+/* The source of the program's native kernel `kernel` (EC_NATIVE_WHOLE or
+ * EC_NATIVE_PAIRS; host copy, valid until ec_program_free; *len without a
+ * terminating zero, which follows it).  EC_ERR_ARG if the program has no
+ * such kernel. */
+ec_status ec_program_native_source(const ec_program *prog, int kernel, const char **src, size_t *len);
 
 /* The current device's program pool: chunks of device memory allocated,
  * distinct records held, and bytes of them in use (in 256-byte granules).

@@ -23,13 +23,14 @@ __all__ = [
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
     "SPLIT_ROWS", "SPLIT_PAIRS", "SPLIT_PASSES", "SPLIT_STAGED", "SCHED_PUSH", "SCHED_GREEDY",
-    "ec_program_upload_many", "ec_program_pool_stats",
+    "ec_program_upload_many", "ec_program_pool_stats", "NATIVE_WHOLE", "NATIVE_PAIRS",
 ]
 
 LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
 COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
 SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS, SPLIT_ROWS, SPLIT_PAIRS, SPLIT_PASSES, SPLIT_STAGED = 0, 1, 2, 3, 4, 5, 6
 SCHED_PUSH, SCHED_GREEDY = 0, 1
+NATIVE_WHOLE, NATIVE_PAIRS = 1, 2
 STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
 
 STATUS = {
@@ -120,7 +121,8 @@ def lib():
                                        ctypes.c_size_t, vp]
         L.ec_program_upload.argtypes = [vp]
         L.ec_program_upload_many.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
-        L.ec_program_native_source.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t)]
+        L.ec_program_native_source.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                               ctypes.POINTER(ctypes.c_size_t)]
         L.ec_program_pool_stats.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_size_t)]
         L.ec_batch_reserve.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
@@ -268,10 +270,11 @@ class Program:
         does it, synchronously)."""
         _check(lib().ec_program_upload(self._h), "ec_program_upload")
 
-    def native_source(self) -> str:
-        """Source of the program's native kernel (EcError if it has none)."""
+    def native_source(self, kernel: int = 1) -> str:
+        """Source of the program's native kernel ``kernel`` (NATIVE_WHOLE or
+        NATIVE_PAIRS; EcError if it has none)."""
         src, n = ctypes.c_char_p(), ctypes.c_size_t()
-        _check(lib().ec_program_native_source(self._h, ctypes.byref(src), ctypes.byref(n)),
+        _check(lib().ec_program_native_source(self._h, kernel, ctypes.byref(src), ctypes.byref(n)),
                "ec_program_native_source")
         return src.value[:n.value].decode()
 
@@ -296,7 +299,7 @@ class Program:
 def ec_compile_slp(n: int, p: int, gen, erased=(), level: int = LEVEL_CO_FU_SCHED, slot_budget: int = 0,
                    compress: int = COMPRESS_XORREPAIR, block_strips: int = 0,
                    prefetch: int | None = None, split: int = SPLIT_AUTO, scheduler: int = SCHED_PUSH,
-                   native: bool = False) -> Program:
+                   native: int = 0) -> Program:
     er = list(erased)
     er_arr = (ctypes.c_int * max(1, len(er)))(*er)
     opts = CompileOpts(level, slot_budget, compress, block_strips,

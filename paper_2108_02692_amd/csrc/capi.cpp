@@ -146,13 +146,14 @@ ec_status launch_staged(const ec_program *prog, ExecArgs &a, int n_cus, ec_strea
   return EC_OK;
 }
 
-// The whole program as its native kernel, one wave per tile: as many
-// workgroups as stay resident, each looping over tiles.
-ec_status launch_native(ec_program *prog, const ExecArgs &a, int n_cus, ec_stream stream) {
+// Native kernel `which` (0: the whole program, one wave per tile; 1: the
+// pair parts, one wave per (tile, part)): as many workgroups as stay
+// resident, each looping over its work items.
+ec_status launch_native(ec_program *prog, int which, const ExecArgs &a, int n_cus, ec_stream stream) {
   int dev = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
   ec_status st = EC_OK;
-  hipFunction_t fn = prog->native_function(dev, &per_cu, &st);
+  hipFunction_t fn = prog->native_function(dev, which, &per_cu, &st);
   if (!fn) return st;
   ec::NativeArgs na{};
   for (int b = 0; b < kMaxBlocks; ++b) na.blk[b] = a.blk[b];
@@ -161,7 +162,9 @@ ec_status launch_native(ec_program *prog, const ExecArgs &a, int n_cus, ec_strea
   na.seg_shift = a.seg_shift;
   na.seg_mask = a.seg_mask;
   na.seg_tiles = a.seg_tiles;
-  const int grid = (int)std::min<uint64_t>(((uint64_t)a.n_tiles + 3) / 4, (uint64_t)n_cus * per_cu);
+  na.n_parts = which ? (uint32_t)prog->pair_parts.size() : 1u;
+  const uint64_t n_work = (uint64_t)a.n_tiles * na.n_parts;
+  const int grid = (int)std::min<uint64_t>((n_work + 3) / 4, (uint64_t)n_cus * per_cu);
   return ec::native_launch(fn, na, grid, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
 }
 
@@ -203,22 +206,39 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   } else if (prog->split == EC_SPLIT_PASSES) {
     if (ns) off = &prog->pass_part_off;
   } else if (prog->split == EC_SPLIT_AUTO) {
-    // The finest set that fits: row or pair parts while there are at most
-    // two waves per SIMD (their chains run side by side), block parts while
-    // all their waves are resident; else pass parts when the program needs
-    // several passes over the inputs.
     const uint64_t fine = 2ull * 4 * (uint64_t)n_cus;
-    if (nr && a.n_tiles * nr <= fine) off = &prog->row_part_off;
-    else if (np && a.n_tiles * np <= fine) off = &prog->pair_part_off;
-    else if (nb && a.n_tiles * nb <= waves) off = &prog->part_off;
-    else if (ns) off = &prog->pass_part_off;
+    const bool nat_whole = !prog->native_code[0].empty(), nat_pairs = !prog->native_code[1].empty();
+    if (nat_pairs && np && a.n_tiles * np <= fine / 2) {
+      // With native kernels: pair parts up to one wave per SIMD, else the
+      // whole program.  Measured on RS(10,4) encodes: 64 - 512 KiB blocks
+      // 7.3 - 9.5 us with native pair parts against 11 - 15 us with the
+      // interpreter's row parts; 1 - 8 MiB 14 - 23 us with the native whole
+      // program against 19 - 35 us with the interpreter's splits.
+      off = &prog->pair_part_off;
+    } else if (nat_whole) {
+      off = nullptr;
+    } else if (nr && a.n_tiles * nr <= fine) {
+      // The finest set that fits: row or pair parts while there are at most
+      // two waves per SIMD (their chains run side by side), block parts
+      // while all their waves are resident; else pass parts when the
+      // program needs several passes over the inputs.
+      off = &prog->row_part_off;
+    } else if (np && a.n_tiles * np <= fine) {
+      off = &prog->pair_part_off;
+    } else if (nb && a.n_tiles * nb <= waves) {
+      off = &prog->part_off;
+    } else if (ns) {
+      off = &prog->pass_part_off;
+    }
   }
   if (off) {
     a.n_parts = (uint32_t)off->size();
     for (uint32_t q = 0; q < a.n_parts; ++q) a.part_off[q] = (*off)[q];
-  } else if (!prog->native_code.empty()) {
-    return launch_native(const_cast<ec_program *>(prog), a, n_cus, stream);
   }
+  // native kernels, where the program has one for the launch's split
+  if (off == &prog->pair_part_off && !prog->native_code[1].empty())
+    return launch_native(const_cast<ec_program *>(prog), 1, a, n_cus, stream);
+  if (!off && !prog->native_code[0].empty()) return launch_native(const_cast<ec_program *>(prog), 0, a, n_cus, stream);
   // As many workgroups as stay resident (4 waves each, one per SIMD, times
   // the waves per SIMD the slot budget allows), each looping over its work
   // items: measured 3-6% faster than one workgroup per 4 tiles.
@@ -268,7 +288,8 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (opts) o = *opts;
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.scheduler > EC_SCHED_GREEDY) return EC_ERR_UNSUPPORTED;
-  if (o.native > 1 || (o.native && o.split == EC_SPLIT_STAGED)) return EC_ERR_UNSUPPORTED;
+  if (o.native > (EC_NATIVE_WHOLE | EC_NATIVE_PAIRS) || (o.native && o.split == EC_SPLIT_STAGED))
+    return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
   if (o.split > EC_SPLIT_STAGED) return EC_ERR_UNSUPPORTED;
@@ -526,11 +547,20 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
-  // The native kernel: the whole program's records as straight-line code.
-  if (o.native) {
+  // Native kernels: the whole program's records, and the pair parts'
+  // (when the program has them), as straight-line code.
+  for (int which = 0; which < 2; ++which) {
+    if (!(o.native & (which ? EC_NATIVE_PAIRS : EC_NATIVE_WHOLE))) continue;
+    std::vector<std::vector<uint32_t>> parts;
+    if (which == 0) {
+      parts.push_back(prog->code.words);
+    } else {
+      for (const PushCode &part : prog->pair_parts) parts.push_back(part.words);
+    }
+    if (parts.empty()) continue;
     std::string log;
-    prog->native_src = ec::native_source(prog->code.words, prog->slots, n_in + n_out);
-    const ec_status st = ec::native_compile(prog->native_src, &prog->native_code, &log);
+    prog->native_src[which] = ec::native_source(parts, prog->slots, n_in + n_out);
+    const ec_status st = ec::native_compile(prog->native_src[which], &prog->native_code[which], &log);
     if (st != EC_OK) return st;
   }
 
@@ -560,7 +590,8 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_pass_parts = (uint32_t)prog->pass_parts.size();
   info.scheduler = o.scheduler;
   info.n_stage_parts = (uint32_t)prog->stage_parts.size();
-  info.native = prog->native_code.empty() ? 0u : 1u;
+  info.native = (prog->native_code[0].empty() ? 0u : (uint32_t)EC_NATIVE_WHOLE) |
+                (prog->native_code[1].empty() ? 0u : (uint32_t)EC_NATIVE_PAIRS);
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -665,18 +696,21 @@ ec_status ec_program_upload(ec_program *prog) {
   if (!prog) return EC_ERR_ARG;
   ec_status st = EC_OK;
   if (!prog->device_words(&st)) return st;
-  if (!prog->native_code.empty()) {
-    int dev = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
-    if (!prog->native_function(dev, &per_cu, &st)) return st;
-  }
+  for (int which = 0; which < 2; ++which)
+    if (!prog->native_code[which].empty()) {
+      int dev = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
+      if (!prog->native_function(dev, which, &per_cu, &st)) return st;
+    }
   return EC_OK;
 }
 
-ec_status ec_program_native_source(const ec_program *prog, const char **src, size_t *len) {
-  if (!prog || !src || !len || prog->native_src.empty()) return EC_ERR_ARG;
-  *src = prog->native_src.c_str();
-  *len = prog->native_src.size();
+ec_status ec_program_native_source(const ec_program *prog, int kernel, const char **src, size_t *len) {
+  if (!prog || !src || !len || (kernel != EC_NATIVE_WHOLE && kernel != EC_NATIVE_PAIRS)) return EC_ERR_ARG;
+  const std::string &s = prog->native_src[kernel == EC_NATIVE_PAIRS ? 1 : 0];
+  if (s.empty()) return EC_ERR_ARG;
+  *src = s.c_str();
+  *len = s.size();
   return EC_OK;
 }
 
@@ -699,7 +733,8 @@ ec_status ec_program_upload_many(ec_program *const *progs, int n) {
     ec_status st = EC_OK;
     if (!progs[i]->device_words(dev, &st)) return st;
     int per_cu = 0;
-    if (!progs[i]->native_code.empty() && !progs[i]->native_function(dev, &per_cu, &st)) return st;
+    for (int which = 0; which < 2; ++which)
+      if (!progs[i]->native_code[which].empty() && !progs[i]->native_function(dev, which, &per_cu, &st)) return st;
   }
   return EC_OK;
 }

@@ -88,6 +88,7 @@ typedef uint32_t v32u __attribute__((ext_vector_type(32)));
 struct NativeArgs {
   uint64_t blk[32];
   uint32_t sl, n_tiles, seg_shift, seg_mask, seg_tiles;
+  uint32_t n_parts;
 };
 // work item k -> tile: groups of 4 neighbouring tiles taken from
 // 2^seg_shift segments in turn (the interpreter's order)
@@ -99,7 +100,7 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t k, uint32_t shift, uint32_t
 
 }  // namespace
 
-std::string native_source(const std::vector<uint32_t> &words, int K, int n_blocks) {
+std::string native_source(const std::vector<std::vector<uint32_t>> &parts, int K, int n_blocks) {
   const auto groups = slot_groups(K);
   std::string decl = "  v4u acc;", outs = "\"+{v[0:3]}\"(acc)", init_outs = "\"={v[0:3]}\"(acc)";
   for (size_t i = 0; i < groups.size(); ++i) {
@@ -126,17 +127,30 @@ std::string native_source(const std::vector<uint32_t> &words, int K, int n_block
   s += "  asm volatile(\"" + init + "\" : " + init_outs + ");\n";
   for (int b = 0; b < n_blocks; ++b) s += fmt("  const uint64_t b%d = a.blk[%d];\n", b, b);
   s += "  const uint32_t voff = lane * 16u;\n";
-  s += "  for (uint32_t k = wave; k < a.n_tiles; k += n_waves) {\n";
-  s += "    const uint32_t toff = tile_of(k, a.seg_shift, a.seg_mask, a.seg_tiles) * 1024u;\n";
+  const bool split = parts.size() > 1;
+  s += "  const uint32_t n_work = a.n_tiles * a.n_parts;\n";
+  s += "  for (uint32_t k = wave; k < n_work; k += n_waves) {\n";
+  if (split) {
+    s += "    const uint32_t kt = k / a.n_parts, part = k - kt * a.n_parts;\n";
+  } else {
+    s += "    const uint32_t kt = k;\n";
+  }
+  s += "    const uint32_t toff = tile_of(kt, a.seg_shift, a.seg_mask, a.seg_tiles) * 1024u;\n";
   s += "    // lanes past the end of a ragged last tile sit the tile out\n";
   s += "    if (toff + voff < a.sl) {\n";
   s += "      // byte offset of this lane's 16 bytes of strip c in every block\n";
   for (int c = 0; c < 8; ++c) s += fmt("      const uint32_t o%d = toff + voff + %du * a.sl;\n", c, c);
-  s += "      asm volatile(\n";
-  s += body(words);
-  s += "        : " + outs + "\n";
-  s += "        : " + ins + "\n";
-  s += "        : \"memory\");\n";
+  if (split) s += "      switch (part) {\n";
+  for (size_t q = 0; q < parts.size(); ++q) {
+    if (split) s += fmt("      case %d:\n", (int)q);
+    s += "      asm volatile(\n";
+    s += body(parts[q]);
+    s += "        : " + outs + "\n";
+    s += "        : " + ins + "\n";
+    s += "        : \"memory\");\n";
+    if (split) s += "      break;\n";
+  }
+  if (split) s += "      }\n";
   s += "    }\n  }\n}\n";
   return s;
 }

@@ -25,15 +25,19 @@ namespace ec {
 struct NativeArgs {
   uint64_t blk[32];
   uint32_t sl, n_tiles, seg_shift, seg_mask, seg_tiles;
+  uint32_t n_parts;  // work item k: part k % n_parts of tile k / n_parts
 };
 
 // Name of the kernel in every generated source.
 constexpr const char *kNativeKernel = "ec_native_kernel";
 
-// The source of the native kernel for program words `words` (records for
-// `slots` register slots, reading and writing n_blocks blocks).  Strip
-// loads and stores are non-temporal, as the interpreter's.
-std::string native_source(const std::vector<uint32_t> &words, int slots, int n_blocks);
+// The source of the native kernel for `parts`, the records of one program
+// or of the parts of a row split (records for `slots` register slots,
+// reading and writing n_blocks blocks): with several parts, work item k
+// runs part k % n_parts on tile k / n_parts, as the interpreter's split
+// launches do.  Strip loads and stores are non-temporal, as the
+// interpreter's.
+std::string native_source(const std::vector<std::vector<uint32_t>> &parts, int slots, int n_blocks);
 
 // Compiles `src` for gfx950; the code object in *code.  EC_ERR_UNSUPPORTED
 // with the compiler's log in *log when it fails.

@@ -39,9 +39,10 @@ struct ec_program {
   std::vector<uint32_t> pair_part_off;   // word offset of each pair part in the image
   std::vector<uint32_t> pass_part_off;   // word offset of each pass part in the image
   std::vector<uint32_t> stage_part_off;  // word offset of each stage part in the image
-  std::string native_src;                // native kernel source (empty: none)
-  std::vector<char> native_code;         // its gfx950 code object
-  std::map<int, std::pair<hipFunction_t, int>> native_fn;  // device -> kernel, workgroups per CU
+  // native kernels: [0] the whole program, [1] its pair parts (empty: none)
+  std::string native_src[2];
+  std::vector<char> native_code[2];
+  std::map<std::pair<int, int>, std::pair<hipFunction_t, int>> native_fn;  // (device, kernel) -> kernel, workgroups per CU
   int split = EC_SPLIT_AUTO;
   ec_program_info info{};
   std::mutex mu;
@@ -55,17 +56,18 @@ struct ec_program {
     for (auto &kv : dev_words) ec::pool_release(kv.first, kv.second);
   }
 
-  // The native kernel on device `dev` (the current device), loaded on
-  // first use; null and *st set if it cannot be loaded.
-  hipFunction_t native_function(int dev, int *per_cu, ec_status *st) {
+  // Native kernel `which` (0 whole program, 1 pair parts) on device `dev`
+  // (the current device), loaded on first use; null and *st set if it
+  // cannot be loaded.
+  hipFunction_t native_function(int dev, int which, int *per_cu, ec_status *st) {
     std::lock_guard<std::mutex> g(mu);
-    auto it = native_fn.find(dev);
+    auto it = native_fn.find({dev, which});
     if (it == native_fn.end()) {
       hipFunction_t fn = nullptr;
       int n = 0;
-      *st = ec::native_function(dev, native_code, &fn, &n);
+      *st = ec::native_function(dev, native_code[which], &fn, &n);
       if (*st != EC_OK) return nullptr;
-      it = native_fn.emplace(dev, std::make_pair(fn, n)).first;
+      it = native_fn.emplace(std::make_pair(dev, which), std::make_pair(fn, n)).first;
     }
     *per_cu = it->second.second;
     return it->second.first;

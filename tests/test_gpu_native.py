@@ -1,10 +1,11 @@
 """Native kernels on the GPU (ec_compile_opts.native): byte for byte
 against the oracle on codecs from 2 to 32 blocks, both levels, slot budgets
 from 24 to 60, encodes and decodes, block sizes from one lane of one tile
-(128 B) through ragged tails to several MiB; captured in a HIP graph and
-replayed with new inputs; and launches that split a short stripe's rows
-(which keep the interpreter) beside native ones.  Generators and expected
-values come from the oracle; outputs are poisoned first."""
+(128 B) through ragged tails to several MiB; the pair-part kernel and the
+default split with native kernels; captured in a HIP graph and replayed
+with new inputs; and explicit row splits, which keep the interpreter.
+Generators and expected values come from the oracle; outputs are poisoned
+first."""
 import os
 
 import numpy as np
@@ -59,12 +60,16 @@ def test_native_matches_oracle(n, p, er, level, K):
 
 
 def test_native_beside_split_launches():
-    """The default split: short stripes run the interpreter's parts, long
-    ones the native kernel; both equal the oracle."""
+    """With the whole-program kernel the default split runs it at every
+    size; an explicit split (row or block parts) keeps the interpreter on
+    the same program.  All equal the oracle."""
     n, p = 10, 4
     for er in ((), (1, 5, 12)):
         prog = E.ec_compile_slp(n, p, oracle_gen(n, p), list(er), native=True)
         run_and_check(prog, n, p, er, (8192, 1 << 20, 16 << 20), seed=7 + len(er))
+        for split in (E.SPLIT_ROWS, E.SPLIT_ALWAYS):
+            prog = E.ec_compile_slp(n, p, oracle_gen(n, p), list(er), native=True, split=split)
+            run_and_check(prog, n, p, er, (8192, (1 << 20) + 128), seed=11 + split)
 
 
 @pytest.mark.parametrize("S", [1 << 20, 16 << 20])
@@ -103,3 +108,49 @@ def test_native_graph_replay(S):
             assert np.array_equal(par[j].cpu().numpy(), blocks[n + j]), "replay %d parity %d" % (rep, j)
         for j, e in enumerate(dec.out_blocks):
             assert np.array_equal(rec[j].cpu().numpy(), blocks[e]), "replay %d block %d" % (rep, e)
+
+
+@pytest.mark.parametrize("n,p,er,level", [(10, 4, (), E.LEVEL_PLAIN), (10, 4, (), E.LEVEL_CO_FU_SCHED),
+                                          (10, 4, (0, 3, 11, 12), E.LEVEL_CO_FU_SCHED), (6, 3, (1, 7), E.LEVEL_PLAIN),
+                                          (14, 4, (5,), E.LEVEL_PLAIN)])
+def test_native_pairs_and_default_split(n, p, er, level):
+    """Both native kernels under the default split (pair parts on short
+    stripes, the whole program beyond), and the pair kernel forced on every
+    size: byte for byte against the oracle, ragged tails included."""
+    gen = oracle_gen(n, p)
+    both = E.ec_compile_slp(n, p, gen, list(er), level=level, native=E.NATIVE_WHOLE | E.NATIVE_PAIRS)
+    assert both.info["native"] == E.NATIVE_WHOLE | E.NATIVE_PAIRS
+    run_and_check(both, n, p, er, (128, 8320, 64 << 10, (512 << 10) + 128, 1 << 20, (2 << 20) + 1152, 8 << 20),
+                  seed=n + p + level)
+    pairs = E.ec_compile_slp(n, p, gen, list(er), level=level, native=E.NATIVE_PAIRS, split=E.SPLIT_PAIRS)
+    assert pairs.info["native"] == E.NATIVE_PAIRS
+    run_and_check(pairs, n, p, er, (8320, (1 << 20) + 128, 3 << 20), seed=7 * n + p)
+
+
+def test_native_pairs_graph_replay():
+    """The pair kernel captured in a HIP graph after the upload loads it,
+    replayed with new inputs."""
+    n, p, S = 10, 4, 256 << 10
+    gen = oracle_gen(n, p)
+    G = oracle.cauchy(n, p)
+    enc = E.ec_compile_slp(n, p, gen, native=E.NATIVE_PAIRS)
+    enc.upload()
+    d, par = W.empty_blocks(n, S), W.empty_blocks(p, S)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        E.ec_encode(enc, d, par, S, s)
+    for rep in range(3):
+        data = W.host_blocks(n, S, seed=300 + rep)
+        want = oracle.encode(G, n, p, data, threads=THREADS)
+        for t, x in zip(d, data):
+            t.copy_(torch.from_numpy(x))
+        for t in par:
+            t.fill_(0x66 + rep)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        for j in range(p):
+            assert np.array_equal(par[j].cpu().numpy(), want[j]), "replay %d parity %d" % (rep, j)

@@ -19,17 +19,27 @@ from test_compiler import oracle_rows
 ASM = re.compile(r'^\s*"(.*)\\n\\t"$')
 
 
-def asm_body(src):
-    """The instructions of the per-tile asm statement."""
+def asm_bodies(src):
+    """The instructions of each per-tile asm statement (one per part)."""
     lines = src.splitlines()
-    start = next(i for i, ln in enumerate(lines) if ln.strip() == "asm volatile(")
     out = []
-    for ln in lines[start + 1:]:
-        m = ASM.match(ln)
-        if not m:
-            break
-        out.append(m.group(1))
+    for i, ln in enumerate(lines):
+        if ln.strip() != "asm volatile(":
+            continue
+        body = []
+        for ln2 in lines[i + 1:]:
+            m = ASM.match(ln2)
+            if not m:
+                break
+            body.append(m.group(1))
+        out.append(body)
     return out
+
+
+def asm_body(src):
+    bodies = asm_bodies(src)
+    assert len(bodies) == 1
+    return bodies[0]
 
 
 def run_symbolic(body, n_in, tiles=2):
@@ -122,6 +132,36 @@ def test_native_code_is_the_program(n, p, er, level, K):
         assert sum(e[0] == "load" for e in events) > n_in * 8
 
 
+@pytest.mark.parametrize("n,p,er,level", [(10, 4, (), E.LEVEL_PLAIN), (10, 4, (2, 4, 5, 6), E.LEVEL_CO_FU_SCHED),
+                                          (6, 3, (1, 7), E.LEVEL_PLAIN)])
+def test_native_pair_kernel_is_the_pair_parts(n, p, er, level):
+    """The pair-part kernel: one asm statement per pair part, each the
+    part's records; run symbolically they store every output strip once,
+    in consecutive pairs of rows, with the bitmatrix row's value."""
+    gen = E.ec_matrix_cauchy(n, p)
+    prog = E.ec_compile_slp(n, p, gen, er, level=level, native=E.NATIVE_WHOLE | E.NATIVE_PAIRS)
+    info = prog.info
+    assert info["native"] == E.NATIVE_WHOLE | E.NATIVE_PAIRS
+    n_in = len(prog.in_blocks)
+    bodies = asm_bodies(prog.native_source(E.NATIVE_PAIRS))
+    assert len(bodies) == info["n_pair_parts"] > 1
+    rows = oracle_rows(gen, n, p, er)
+    got = {}
+    first_pair = info["n_parts"] + info["n_row_parts"]
+    for q, body in enumerate(bodies):
+        stores, reg, events = run_symbolic(body, n_in)
+        keys = sorted(8 * b + j for b, j in stores)
+        assert keys == list(range(len(got), len(got) + len(keys))) and len(keys) % 2 == 0
+        assert not set(keys) & set(got)
+        got.update({8 * b + j: v for (b, j), v in stores.items()})
+        assert all(reg.get(v, 0) == 0 for v in range(4, 4 + 4 * info["slots"]))
+        assert events == record_events(prog.part_bytecode(first_pair + q))
+    assert [got[r] for r in range(len(rows))] == rows
+    # a program without pair parts gets no pair kernel
+    one = E.ec_compile_slp(n, p, gen, er, level=level, native=E.NATIVE_PAIRS, split=E.SPLIT_NEVER)
+    assert one.info["native"] == 0
+
+
 def test_native_options_and_errors():
     gen = E.ec_matrix_cauchy(10, 4)
     plain = E.ec_compile_slp(10, 4, gen)
@@ -129,7 +169,7 @@ def test_native_options_and_errors():
     with pytest.raises(E.EcError) as e:
         plain.native_source()
     assert e.value.name == "EC_ERR_ARG"
-    for kw in ({"native": 2}, {"native": 1, "split": E.SPLIT_STAGED}):
+    for kw in ({"native": 4}, {"native": 1, "split": E.SPLIT_STAGED}):
         with pytest.raises(E.EcError) as e:
             E.ec_compile_slp(10, 4, gen, **kw)
         assert e.value.name == "EC_ERR_UNSUPPORTED"
@@ -137,3 +177,6 @@ def test_native_options_and_errors():
     a = E.ec_compile_slp(10, 4, gen, [1, 2], native=True).native_source()
     b = E.ec_compile_slp(10, 4, gen, [1, 2], native=True).native_source()
     assert a == b and "ec_native_kernel" in a
+    with pytest.raises(E.EcError) as e:  # compiled without the pair kernel
+        E.ec_compile_slp(10, 4, gen, [1, 2], native=True).native_source(E.NATIVE_PAIRS)
+    assert e.value.name == "EC_ERR_ARG"
