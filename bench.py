@@ -616,7 +616,8 @@ def bench_serving(args, batched_GB_s=None):
     from paper_2108_02692_amd import serve
     c0, _, _ = E.ec_program_pool_stats()
     t0 = time.perf_counter()
-    server = serve.Server()
+    native = args.exec == "native"
+    server = serve.Server(native_encodes=native)
     setup_s = time.perf_counter() - t0
     c1, images, pool_bytes = E.ec_program_pool_stats()
     import torch
@@ -647,7 +648,8 @@ def bench_serving(args, batched_GB_s=None):
     # of its codecs): the device allocations the upload made, the distinct
     # records and their bytes
     res["setup"] = {"seconds": setup_s, "programs": len(server.cache), "pool_allocations": c1 - c0,
-                    "pool_records": images, "pool_bytes": pool_bytes}
+                    "pool_records": images, "pool_bytes": pool_bytes,
+                    "native_kernels": "the codecs' encode programs" if native else "none"}
     if batched_GB_s:
         res["drain_vs_batched"] = res["drain_GB_s"] / batched_GB_s
     return res

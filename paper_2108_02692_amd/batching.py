@@ -42,12 +42,17 @@ class StripeSpec:
 class ProgramCache:
     """Compiled programs keyed by (n, p, erased, level, slots, scheduler);
     thread-safe.  The generator of each codec is ``generator_fn(n, p)``
-    ((n+p) x n rows), by default the library's Cauchy matrix."""
+    ((n+p) x n rows), by default the library's Cauchy matrix.  The
+    (n, p, erased) in ``native_keys`` are compiled with the native kernels
+    ``native`` (EC_NATIVE_* bits) as well."""
 
-    def __init__(self, level: int = LEVEL_PLAIN, slots: int = 40, generator_fn=None, scheduler: int = SCHED_PUSH):
+    def __init__(self, level: int = LEVEL_PLAIN, slots: int = 40, generator_fn=None, scheduler: int = SCHED_PUSH,
+                 native_keys=(), native: int = 0):
         self.level = level
         self.slots = slots
         self.scheduler = scheduler
+        self.native_keys = {(n, p, tuple(er)) for n, p, er in native_keys}
+        self.native = native
         self._gen_fn = generator_fn or ec_matrix_cauchy
         self._progs = {}
         self._gens = {}
@@ -65,8 +70,9 @@ class ProgramCache:
         with self._lock:
             prog = self._progs.get(key)
         if prog is None:
+            native = self.native if (n, p, tuple(erased)) in self.native_keys else 0
             prog = ec_compile_slp(n, p, self.generator(n, p), list(erased), level=self.level,
-                                  slot_budget=self.slots, scheduler=self.scheduler)
+                                  slot_budget=self.slots, scheduler=self.scheduler, native=native)
             with self._lock:
                 prog = self._progs.setdefault(key, prog)
         return prog

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2108_02692_amd as E
 from paper_2108_02692_amd import serve as SV
 
 pytestmark = pytest.mark.gpu
@@ -154,3 +155,41 @@ def test_native_loop_mixed_slot_budgets():
         want = np.concatenate(oracle.apply(D, [np.ascontiguousarray(b) for b in data]))
         assert np.array_equal(got[i], want), "request %d %s" % (i, c)
     srv.free()
+
+
+def test_native_encodes_in_the_loop():
+    """A server whose encode programs have native kernels: requests served
+    alone run them, batched ones the interpreter; every output equals the
+    oracle."""
+    pool_bytes = 8 << 20
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14)
+    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    pool_h = pool.cpu().numpy()
+    server = SV.Server(generator_fn=oracle.cauchy, budget_bytes=64 << 20, n_slots=4, max_batch=16, warm=False,
+                       native_encodes=True)
+    for n, p in ((10, 4), (6, 3)):
+        assert server.cache.get(n, p).info["native"] == E.NATIVE_WHOLE | E.NATIVE_PAIRS
+        assert server.cache.get(n, p, (1,)).info["native"] == 0
+    reqs = SV.make_requests(0.01, 20000.0, seed=9, pool_ptr=pool.data_ptr(), pool_bytes=pool_bytes, hi=1 << 20)
+    assert any(not r.erased for r in reqs) and any(r.erased for r in reqs)
+    got = {}
+
+    def grab(done):
+        got.update({r.rid: o for r, o in zip(done, outputs_of(server, done))})
+    server.serve(reqs, on_done=grab)
+    torch.cuda.synchronize()
+    for r in [r for r in reqs if not r.erased] + reqs[::5]:
+        want = expected(server, r, pool_h, pool.data_ptr())
+        for j in range(r.n_out):
+            assert np.array_equal(got[r.rid][j], want[j]), "request %d output %d" % (r.rid, j)
+    # the same requests all at once: batches of several requests
+    got.clear()
+    for r in reqs:
+        r.arrival = 0.0
+    server.serve(reqs, realtime=False, on_done=grab)
+    torch.cuda.synchronize()
+    for r in reqs[::3]:
+        want = expected(server, r, pool_h, pool.data_ptr())
+        for j in range(r.n_out):
+            assert np.array_equal(got[r.rid][j], want[j]), "drain: request %d output %d" % (r.rid, j)
