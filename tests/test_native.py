@@ -180,3 +180,14 @@ def test_native_options_and_errors():
     with pytest.raises(E.EcError) as e:  # compiled without the pair kernel
         E.ec_compile_slp(10, 4, gen, [1, 2], native=True).native_source(E.NATIVE_PAIRS)
     assert e.value.name == "EC_ERR_ARG"
+
+
+def test_program_cache_native_keys():
+    """A cache compiles exactly its native keys with native kernels (the
+    serving loop's encode programs); the rest stay interpreter-only."""
+    from paper_2108_02692_amd.batching import ProgramCache
+    cache = ProgramCache(level=E.LEVEL_CO_FU_SCHED, slots=38, native_keys=[(6, 3, ())], native=E.NATIVE_WHOLE)
+    assert cache.get(6, 3).info["native"] == E.NATIVE_WHOLE
+    assert cache.get(6, 3, (1,)).info["native"] == 0
+    assert cache.get(10, 4).info["native"] == 0
+    assert cache.get(6, 3) is cache.get(6, 3, ())
