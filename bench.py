@@ -588,7 +588,7 @@ def bench_small(args, stream):
     """RS(10,4) encode of 10 x 1 MiB blocks: 14 MiB per launch, which the
     caches hold and the launch overhead dominates (not a roofline number);
     the interpreter, and with --exec native the programs' native kernels
-    (the default split then runs the native whole program at this size)."""
+    (the default split then runs the native block parts at this size)."""
     import paper_2108_02692_amd as E
     from paper_2108_02692_amd import workloads as W
     n, p, S = 10, 4, 1 << 20
@@ -597,7 +597,7 @@ def bench_small(args, stream):
     parity = W.empty_blocks(p, S)
     res = {"workload": "RS(10,4) encode, 10 x 1 MiB"}
     for level, tag in ((E.LEVEL_CO_FU_SCHED, "comp"), (E.LEVEL_PLAIN, "plain")):
-        for native in ((0, E.NATIVE_WHOLE | E.NATIVE_PAIRS) if args.exec == "native" else (0,)):
+        for native in ((0, E.NATIVE_WHOLE | E.NATIVE_PAIRS | E.NATIVE_BLOCKS) if args.exec == "native" else (0,)):
             prog = E.ec_compile_slp(n, p, gen, level=level, native=native)
             ms = time_launches(lambda: E.ec_encode(prog, data, parity, S, stream), max(args.steps, 100),
                                args.warmup, stream)

@@ -111,8 +111,9 @@ typedef struct {
 
 /* Native kernels to compile (ec_compile_opts.native, ec_program_info.native). */
 enum {
-  EC_NATIVE_WHOLE = 1, /* the whole program: launches with no row split */
-  EC_NATIVE_PAIRS = 2  /* the pair parts (when the program has them): launches that split into pairs */
+  EC_NATIVE_WHOLE = 1,  /* the whole program: launches with no row split */
+  EC_NATIVE_PAIRS = 2,  /* the pair parts (when the program has them): launches that split into pairs */
+  EC_NATIVE_BLOCKS = 4  /* the block parts (when the program has them): launches that split by output block */
 };
 
 /* Native kernels (ec_compile_opts.native).  The program's records, a
@@ -128,11 +129,14 @@ enum {
  * pair parts the same way into one kernel (work item k runs pair part
  * k % n_pair_parts of tile k / n_pair_parts), which then runs every launch
  * that splits into pair parts; it takes about 5 s to compile for RS(10,4).
+ * EC_NATIVE_BLOCKS does the same for the block parts (one wave per tile and
+ * output block), which then run every launch that splits by output block.
  * With native kernels EC_SPLIT_AUTO takes the native pair parts while
  * there is at most one wave per SIMD (up to 512 KiB blocks for RS(10,4)),
- * else the native whole program, and only without them the interpreter's
- * rule (EC_SPLIT_AUTO below).  Other split launches and batches keep the
- * interpreter.  The kernel is loaded on
+ * then the native block parts while there are at most two (up to 2 MiB),
+ * else the native whole program, each only where the program has that
+ * kernel, and without them the interpreter's rule (EC_SPLIT_AUTO below).
+ * Row and pass splits and batches keep the interpreter.  The kernel is loaded on
  * a device at the program's upload or first launch there and stays loaded
  * until the process ends (identical kernels are loaded once).  Not with
  * EC_SPLIT_STAGED (EC_ERR_UNSUPPORTED); EC_ERR_UNSUPPORTED also if the
@@ -297,8 +301,8 @@ ec_status ec_program_upload(ec_program *prog);
  * on an error the programs before the failing one stay uploaded. */
 ec_status ec_program_upload_many(ec_program *const *progs, int n);
 
-/* The source of the program's native kernel `kernel` (EC_NATIVE_WHOLE or
- * EC_NATIVE_PAIRS; host copy, valid until ec_program_free; *len without a
+/* The source of the program's native kernel `kernel` (EC_NATIVE_WHOLE,
+ * EC_NATIVE_PAIRS or EC_NATIVE_BLOCKS; host copy, valid until ec_program_free; *len without a
  * terminating zero, which follows it).  EC_ERR_ARG if the program has no
  * such kernel. */
 ec_status ec_program_native_source(const ec_program *prog, int kernel, const char **src, size_t *len);

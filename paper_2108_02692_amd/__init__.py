@@ -23,14 +23,14 @@ __all__ = [
     "LEVEL_PLAIN", "LEVEL_CO", "LEVEL_CO_FU", "LEVEL_CO_FU_SCHED", "COMPRESS_XORREPAIR", "COMPRESS_REPAIR",
     "STAGE_PLAIN", "STAGE_CO", "STAGE_FU", "STAGE_SCHED", "STAGE_EXEC", "SPLIT_AUTO", "SPLIT_NEVER", "SPLIT_ALWAYS",
     "SPLIT_ROWS", "SPLIT_PAIRS", "SPLIT_PASSES", "SPLIT_STAGED", "SCHED_PUSH", "SCHED_GREEDY",
-    "ec_program_upload_many", "ec_program_pool_stats", "NATIVE_WHOLE", "NATIVE_PAIRS",
+    "ec_program_upload_many", "ec_program_pool_stats", "NATIVE_WHOLE", "NATIVE_PAIRS", "NATIVE_BLOCKS",
 ]
 
 LEVEL_PLAIN, LEVEL_CO, LEVEL_CO_FU, LEVEL_CO_FU_SCHED = 0, 1, 2, 3
 COMPRESS_XORREPAIR, COMPRESS_REPAIR = 0, 1
 SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS, SPLIT_ROWS, SPLIT_PAIRS, SPLIT_PASSES, SPLIT_STAGED = 0, 1, 2, 3, 4, 5, 6
 SCHED_PUSH, SCHED_GREEDY = 0, 1
-NATIVE_WHOLE, NATIVE_PAIRS = 1, 2
+NATIVE_WHOLE, NATIVE_PAIRS, NATIVE_BLOCKS = 1, 2, 4
 STAGE_PLAIN, STAGE_CO, STAGE_FU, STAGE_SCHED, STAGE_EXEC = 0, 1, 2, 3, 4
 
 STATUS = {
@@ -271,8 +271,8 @@ class Program:
         _check(lib().ec_program_upload(self._h), "ec_program_upload")
 
     def native_source(self, kernel: int = 1) -> str:
-        """Source of the program's native kernel ``kernel`` (NATIVE_WHOLE or
-        NATIVE_PAIRS; EcError if it has none)."""
+        """Source of the program's native kernel ``kernel`` (NATIVE_WHOLE,
+        NATIVE_PAIRS or NATIVE_BLOCKS; EcError if it has none)."""
         src, n = ctypes.c_char_p(), ctypes.c_size_t()
         _check(lib().ec_program_native_source(self._h, kernel, ctypes.byref(src), ctypes.byref(n)),
                "ec_program_native_source")

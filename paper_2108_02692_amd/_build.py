@@ -28,7 +28,8 @@ def build(verbose: bool = False) -> str:
         procs = []
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+            # hipcc gives .cpp files a device pass too: gfx950 (they hold no kernels)
+            cmd = [HIPCC] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
             if src.endswith(".hip"):
                 cmd = [HIPCC, "-x", "hip"] + DEVICE_FLAGS + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

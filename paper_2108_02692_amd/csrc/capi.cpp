@@ -147,8 +147,8 @@ ec_status launch_staged(const ec_program *prog, ExecArgs &a, int n_cus, ec_strea
 }
 
 // Native kernel `which` (0: the whole program, one wave per tile; 1: the
-// pair parts, one wave per (tile, part)): as many workgroups as stay
-// resident, each looping over its work items.
+// pair parts and 2: the block parts, one wave per (tile, part)): as many
+// workgroups as stay resident, each looping over its work items.
 ec_status launch_native(ec_program *prog, int which, const ExecArgs &a, int n_cus, ec_stream stream) {
   int dev = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
@@ -162,7 +162,7 @@ ec_status launch_native(ec_program *prog, int which, const ExecArgs &a, int n_cu
   na.seg_shift = a.seg_shift;
   na.seg_mask = a.seg_mask;
   na.seg_tiles = a.seg_tiles;
-  na.n_parts = which ? (uint32_t)prog->pair_parts.size() : 1u;
+  na.n_parts = which == 1 ? (uint32_t)prog->pair_parts.size() : which == 2 ? (uint32_t)prog->parts.size() : 1u;
   const uint64_t n_work = (uint64_t)a.n_tiles * na.n_parts;
   const int grid = (int)std::min<uint64_t>((n_work + 3) / 4, (uint64_t)n_cus * per_cu);
   return ec::native_launch(fn, na, grid, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
@@ -208,13 +208,21 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   } else if (prog->split == EC_SPLIT_AUTO) {
     const uint64_t fine = 2ull * 4 * (uint64_t)n_cus;
     const bool nat_whole = !prog->native_code[0].empty(), nat_pairs = !prog->native_code[1].empty();
-    if (nat_pairs && np && a.n_tiles * np <= fine / 2) {
-      // With native kernels: pair parts up to one wave per SIMD, else the
-      // whole program.  Measured on RS(10,4) encodes: 64 - 512 KiB blocks
-      // 7.3 - 9.5 us with native pair parts against 11 - 15 us with the
-      // interpreter's row parts; 1 - 8 MiB 14 - 23 us with the native whole
-      // program against 19 - 35 us with the interpreter's splits.
+    const bool nat_blocks = !prog->native_code[2].empty() && nb;
+    if (nat_pairs && np && a.n_tiles * np <= (nat_blocks ? fine / 4 : fine / 2)) {
+      // With native kernels: pair parts while there is at most half a wave
+      // per SIMD (one without block parts), then block parts up to one wave
+      // per SIMD, else the whole program.  Measured on RS(10,4) encodes and
+      // decodes of {2,4,5,6} (plain / compressed): 16 - 256 KiB blocks 6.6 -
+      // 9.2 us with native pair parts or block parts alike (11 - 15 us with
+      // the interpreter's row parts); 512 KiB 9.0 - 9.3 us with block parts
+      // against 9.7 - 9.8 us with pairs; 1 MiB 9.5 - 9.7 us with block parts
+      // against 13.4 - 15.8 us whole and 15.2 - 15.5 us in pairs; 2 MiB
+      // 10.2 - 10.5 us against 13.9 - 17.4 us whole; 4 MiB 15.0 / 19.1 us
+      // whole against 18.8 / 18.8 us in block parts.
       off = &prog->pair_part_off;
+    } else if (nat_blocks && a.n_tiles * nb <= fine / 2) {
+      off = &prog->part_off;
     } else if (nat_whole) {
       off = nullptr;
     } else if (nr && a.n_tiles * nr <= fine) {
@@ -238,6 +246,8 @@ ec_status launch(const ec_program *prog, const uint8_t *const *in, uint8_t *cons
   // native kernels, where the program has one for the launch's split
   if (off == &prog->pair_part_off && !prog->native_code[1].empty())
     return launch_native(const_cast<ec_program *>(prog), 1, a, n_cus, stream);
+  if (off == &prog->part_off && !prog->native_code[2].empty())
+    return launch_native(const_cast<ec_program *>(prog), 2, a, n_cus, stream);
   if (!off && !prog->native_code[0].empty()) return launch_native(const_cast<ec_program *>(prog), 0, a, n_cus, stream);
   // As many workgroups as stay resident (4 waves each, one per SIMD, times
   // the waves per SIMD the slot budget allows), each looping over its work
@@ -288,7 +298,7 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   if (opts) o = *opts;
   if (o.level > EC_LEVEL_CO_FU_SCHED || o.compress > EC_COMPRESS_REPAIR) return EC_ERR_UNSUPPORTED;
   if (o.scheduler > EC_SCHED_GREEDY) return EC_ERR_UNSUPPORTED;
-  if (o.native > (EC_NATIVE_WHOLE | EC_NATIVE_PAIRS) || (o.native && o.split == EC_SPLIT_STAGED))
+  if (o.native > (EC_NATIVE_WHOLE | EC_NATIVE_PAIRS | EC_NATIVE_BLOCKS) || (o.native && o.split == EC_SPLIT_STAGED))
     return EC_ERR_UNSUPPORTED;
   if (o.slot_budget != 0 && !supported_slots(o.slot_budget)) return EC_ERR_UNSUPPORTED;
   if (o.block_strips > (uint32_t)(8 * n) || o.prefetch > 64) return EC_ERR_ARG;
@@ -547,15 +557,15 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
     prog->image.insert(prog->image.end(), part.words.begin(), part.words.end());
   }
 
-  // Native kernels: the whole program's records, and the pair parts'
-  // (when the program has them), as straight-line code.
-  for (int which = 0; which < 2; ++which) {
-    if (!(o.native & (which ? EC_NATIVE_PAIRS : EC_NATIVE_WHOLE))) continue;
+  // Native kernels: the whole program's records, and the pair parts' and
+  // block parts' (when the program has them), as straight-line code.
+  for (int which = 0; which < ec::kNativeKernels; ++which) {
+    if (!(o.native & (1u << which))) continue;
     std::vector<std::vector<uint32_t>> parts;
     if (which == 0) {
       parts.push_back(prog->code.words);
     } else {
-      for (const PushCode &part : prog->pair_parts) parts.push_back(part.words);
+      for (const PushCode &part : which == 1 ? prog->pair_parts : prog->parts) parts.push_back(part.words);
     }
     if (parts.empty()) continue;
     std::string log;
@@ -590,8 +600,9 @@ ec_status ec_compile_slp(int n, int p, const uint8_t *gen, const int *erased, in
   info.n_pass_parts = (uint32_t)prog->pass_parts.size();
   info.scheduler = o.scheduler;
   info.n_stage_parts = (uint32_t)prog->stage_parts.size();
-  info.native = (prog->native_code[0].empty() ? 0u : (uint32_t)EC_NATIVE_WHOLE) |
-                (prog->native_code[1].empty() ? 0u : (uint32_t)EC_NATIVE_PAIRS);
+  info.native = 0;
+  for (int which = 0; which < ec::kNativeKernels; ++which)
+    if (!prog->native_code[which].empty()) info.native |= 1u << which;
   info.in_blocks = prog->in_blocks.data();
   info.out_blocks = prog->out_blocks.data();
   *out = prog.release();
@@ -696,7 +707,7 @@ ec_status ec_program_upload(ec_program *prog) {
   if (!prog) return EC_ERR_ARG;
   ec_status st = EC_OK;
   if (!prog->device_words(&st)) return st;
-  for (int which = 0; which < 2; ++which)
+  for (int which = 0; which < ec::kNativeKernels; ++which)
     if (!prog->native_code[which].empty()) {
       int dev = 0, per_cu = 0;
       if (hipGetDevice(&dev) != hipSuccess) return EC_ERR_DEVICE;
@@ -706,8 +717,10 @@ ec_status ec_program_upload(ec_program *prog) {
 }
 
 ec_status ec_program_native_source(const ec_program *prog, int kernel, const char **src, size_t *len) {
-  if (!prog || !src || !len || (kernel != EC_NATIVE_WHOLE && kernel != EC_NATIVE_PAIRS)) return EC_ERR_ARG;
-  const std::string &s = prog->native_src[kernel == EC_NATIVE_PAIRS ? 1 : 0];
+  if (!prog || !src || !len) return EC_ERR_ARG;
+  const int which = kernel == EC_NATIVE_WHOLE ? 0 : kernel == EC_NATIVE_PAIRS ? 1 : kernel == EC_NATIVE_BLOCKS ? 2 : -1;
+  if (which < 0) return EC_ERR_ARG;
+  const std::string &s = prog->native_src[which];
   if (s.empty()) return EC_ERR_ARG;
   *src = s.c_str();
   *len = s.size();
@@ -733,7 +746,7 @@ ec_status ec_program_upload_many(ec_program *const *progs, int n) {
     ec_status st = EC_OK;
     if (!progs[i]->device_words(dev, &st)) return st;
     int per_cu = 0;
-    for (int which = 0; which < 2; ++which)
+    for (int which = 0; which < ec::kNativeKernels; ++which)
       if (!progs[i]->native_code[which].empty() && !progs[i]->native_function(dev, which, &per_cu, &st)) return st;
   }
   return EC_OK;

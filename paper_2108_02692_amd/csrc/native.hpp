@@ -28,6 +28,11 @@ struct NativeArgs {
   uint32_t n_parts;  // work item k: part k % n_parts of tile k / n_parts
 };
 
+// Native kernels a program can have: the whole program, its pair parts
+// and its block parts (EC_NATIVE_WHOLE, EC_NATIVE_PAIRS, EC_NATIVE_BLOCKS:
+// kernel k for bit 1 << k).
+constexpr int kNativeKernels = 3;
+
 // Name of the kernel in every generated source.
 constexpr const char *kNativeKernel = "ec_native_kernel";
 

@@ -39,9 +39,10 @@ struct ec_program {
   std::vector<uint32_t> pair_part_off;   // word offset of each pair part in the image
   std::vector<uint32_t> pass_part_off;   // word offset of each pass part in the image
   std::vector<uint32_t> stage_part_off;  // word offset of each stage part in the image
-  // native kernels: [0] the whole program, [1] its pair parts (empty: none)
-  std::string native_src[2];
-  std::vector<char> native_code[2];
+  // native kernels (empty: none): [0] the whole program, [1] its pair
+  // parts, [2] its block parts; kernel k is compiled for EC_NATIVE_* bit 1 << k
+  std::string native_src[ec::kNativeKernels];
+  std::vector<char> native_code[ec::kNativeKernels];
   std::map<std::pair<int, int>, std::pair<hipFunction_t, int>> native_fn;  // (device, kernel) -> kernel, workgroups per CU
   int split = EC_SPLIT_AUTO;
   ec_program_info info{};
@@ -56,7 +57,7 @@ struct ec_program {
     for (auto &kv : dev_words) ec::pool_release(kv.first, kv.second);
   }
 
-  // Native kernel `which` (0 whole program, 1 pair parts) on device `dev`
+  // Native kernel `which` (0 whole program, 1 pair parts, 2 block parts) on device `dev`
   // (the current device), loaded on first use; null and *st set if it
   // cannot be loaded.
   hipFunction_t native_function(int dev, int which, int *per_cu, ec_status *st) {

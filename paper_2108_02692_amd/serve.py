@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import LEVEL_CO_FU_SCHED, NATIVE_PAIRS, NATIVE_WHOLE, ec_batch_build, ec_server_create
+from . import LEVEL_CO_FU_SCHED, NATIVE_BLOCKS, NATIVE_PAIRS, NATIVE_WHOLE, ec_batch_build, ec_server_create
 from .batching import ProgramCache
 
 MAX_OBJECT = 64 << 20  # largest object served (bytes)
@@ -59,8 +59,9 @@ class Server:
     on the device before the clock starts; admission by HBM budget,
     ``n_slots`` launches in flight, each of at most ``max_batch`` requests.
     With ``native_encodes`` the codecs' encode programs (most requests) also
-    get native kernels (whole program and pair parts), which a launch of one
-    request runs; batches and decodes keep the interpreter."""
+    get native kernels (whole program, pair parts and block parts), which
+    a launch of one request runs; batches and decodes keep the
+    interpreter."""
 
     def __init__(self, budget_bytes=16 << 30, n_slots=4, max_batch=DEFAULT_MAX_BATCH, level=LEVEL_CO_FU_SCHED,
                  slots=38, codecs=((10, 4), (6, 3)), warm=True, generator_fn=None, native_encodes=False):
@@ -68,7 +69,7 @@ class Server:
         self.budget = budget_bytes
         self.cache = ProgramCache(level=level, slots=slots, generator_fn=generator_fn,
                                   native_keys=[(n, p, ()) for n, p in codecs] if native_encodes else (),
-                                  native=NATIVE_WHOLE | NATIVE_PAIRS)
+                                  native=NATIVE_WHOLE | NATIVE_PAIRS | NATIVE_BLOCKS)
         if warm:
             self.cache.warm([(n, p, er) for n, p in codecs for er in self.cache.all_patterns(n, p)])
             # every program resident on the device before the clock starts

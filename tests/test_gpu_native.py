@@ -1,8 +1,8 @@
 """Native kernels on the GPU (ec_compile_opts.native): byte for byte
 against the oracle on codecs from 2 to 32 blocks, both levels, slot budgets
 from 24 to 60, encodes and decodes, block sizes from one lane of one tile
-(128 B) through ragged tails to several MiB; the pair-part kernel and the
-default split with native kernels; captured in a HIP graph and replayed
+(128 B) through ragged tails to several MiB; the pair-part and block-part
+kernels and the default split with native kernels; captured in a HIP graph and replayed
 with new inputs; and explicit row splits, which keep the interpreter.
 Generators and expected values come from the oracle; outputs are poisoned
 first."""
@@ -114,17 +114,24 @@ def test_native_graph_replay(S):
                                           (10, 4, (0, 3, 11, 12), E.LEVEL_CO_FU_SCHED), (6, 3, (1, 7), E.LEVEL_PLAIN),
                                           (14, 4, (5,), E.LEVEL_PLAIN)])
 def test_native_pairs_and_default_split(n, p, er, level):
-    """Both native kernels under the default split (pair parts on short
-    stripes, the whole program beyond), and the pair kernel forced on every
-    size: byte for byte against the oracle, ragged tails included."""
+    """The native kernels under the default split (pair parts on short
+    stripes, block parts on longer ones, the whole program beyond), and the
+    pair and block kernels forced on every size: byte for byte against the
+    oracle, ragged tails included."""
     gen = oracle_gen(n, p)
-    both = E.ec_compile_slp(n, p, gen, list(er), level=level, native=E.NATIVE_WHOLE | E.NATIVE_PAIRS)
-    assert both.info["native"] == E.NATIVE_WHOLE | E.NATIVE_PAIRS
-    run_and_check(both, n, p, er, (128, 8320, 64 << 10, (512 << 10) + 128, 1 << 20, (2 << 20) + 1152, 8 << 20),
+    every = E.NATIVE_WHOLE | E.NATIVE_PAIRS | E.NATIVE_BLOCKS
+    allk = E.ec_compile_slp(n, p, gen, list(er), level=level, native=every)
+    want = every if allk.info["n_parts"] else E.NATIVE_WHOLE | E.NATIVE_PAIRS
+    assert allk.info["native"] == want
+    run_and_check(allk, n, p, er, (128, 8320, 64 << 10, (512 << 10) + 128, 1 << 20, (2 << 20) + 1152, 8 << 20),
                   seed=n + p + level)
     pairs = E.ec_compile_slp(n, p, gen, list(er), level=level, native=E.NATIVE_PAIRS, split=E.SPLIT_PAIRS)
     assert pairs.info["native"] == E.NATIVE_PAIRS
     run_and_check(pairs, n, p, er, (8320, (1 << 20) + 128, 3 << 20), seed=7 * n + p)
+    if allk.info["n_parts"]:
+        blocks = E.ec_compile_slp(n, p, gen, list(er), level=level, native=E.NATIVE_BLOCKS, split=E.SPLIT_ALWAYS)
+        assert blocks.info["native"] == E.NATIVE_BLOCKS
+        run_and_check(blocks, n, p, er, (128, 8320, (1 << 20) + 128, 3 << 20), seed=9 * n + p)
 
 
 def test_native_pairs_graph_replay():

@@ -169,7 +169,7 @@ def test_native_encodes_in_the_loop():
     server = SV.Server(generator_fn=oracle.cauchy, budget_bytes=64 << 20, n_slots=4, max_batch=16, warm=False,
                        native_encodes=True)
     for n, p in ((10, 4), (6, 3)):
-        assert server.cache.get(n, p).info["native"] == E.NATIVE_WHOLE | E.NATIVE_PAIRS
+        assert server.cache.get(n, p).info["native"] == E.NATIVE_WHOLE | E.NATIVE_PAIRS | E.NATIVE_BLOCKS
         assert server.cache.get(n, p, (1,)).info["native"] == 0
     reqs = SV.make_requests(0.01, 20000.0, seed=9, pool_ptr=pool.data_ptr(), pool_bytes=pool_bytes, hi=1 << 20)
     assert any(not r.erased for r in reqs) and any(r.erased for r in reqs)

@@ -162,6 +162,35 @@ def test_native_pair_kernel_is_the_pair_parts(n, p, er, level):
     assert one.info["native"] == 0
 
 
+@pytest.mark.parametrize("n,p,er,level", [(10, 4, (), E.LEVEL_PLAIN), (10, 4, (), E.LEVEL_CO_FU_SCHED),
+                                          (10, 4, (0, 3, 11, 12), E.LEVEL_CO_FU_SCHED), (6, 3, (1, 7), E.LEVEL_PLAIN),
+                                          (12, 6, (), E.LEVEL_CO_FU_SCHED)])
+def test_native_block_kernel_is_the_block_parts(n, p, er, level):
+    """The block-part kernel: one asm statement per output block, each that
+    block part's records; run symbolically each stores exactly its block's
+    8 rows, once, with the bitmatrix rows' values."""
+    gen = E.ec_matrix_cauchy(n, p)
+    prog = E.ec_compile_slp(n, p, gen, er, level=level, native=E.NATIVE_BLOCKS)
+    info = prog.info
+    assert info["native"] == E.NATIVE_BLOCKS
+    n_in, n_out = len(prog.in_blocks), len(prog.out_blocks)
+    bodies = asm_bodies(prog.native_source(E.NATIVE_BLOCKS))
+    assert len(bodies) == info["n_parts"] > 1
+    rows = oracle_rows(gen, n, p, er)
+    got = {}
+    for q, body in enumerate(bodies):
+        stores, reg, events = run_symbolic(body, n_in)
+        assert stores and not set(stores) & set(got)
+        got.update(stores)
+        assert all(reg.get(v, 0) == 0 for v in range(4, 4 + 4 * info["slots"]))
+        assert events == record_events(prog.part_bytecode(q))
+    assert sorted(got) == [(r // 8, r % 8) for r in range(8 * n_out)]
+    assert [got[(r // 8, r % 8)] for r in range(len(rows))] == rows
+    # one lost block: no block parts, so no block kernel
+    one = E.ec_compile_slp(n, p, gen, [1], level=level, native=E.NATIVE_BLOCKS)
+    assert one.info["n_parts"] == 0 and one.info["native"] == 0
+
+
 def test_native_options_and_errors():
     gen = E.ec_matrix_cauchy(10, 4)
     plain = E.ec_compile_slp(10, 4, gen)
@@ -169,7 +198,7 @@ def test_native_options_and_errors():
     with pytest.raises(E.EcError) as e:
         plain.native_source()
     assert e.value.name == "EC_ERR_ARG"
-    for kw in ({"native": 4}, {"native": 1, "split": E.SPLIT_STAGED}):
+    for kw in ({"native": 8}, {"native": 1, "split": E.SPLIT_STAGED}):
         with pytest.raises(E.EcError) as e:
             E.ec_compile_slp(10, 4, gen, **kw)
         assert e.value.name == "EC_ERR_UNSUPPORTED"
