@@ -697,9 +697,10 @@ ec_status ec_stripe_stream(const uint8_t *const *in, int n_in, uint8_t *const *o
   set_blocks(a, in, n_in, out, n_out, block_bytes);
   const int n_cus = device_cus();
   if (n_cus <= 0) return EC_ERR_DEVICE;
-  // 8 waves per SIMD (the kernel needs few registers): measured 0.738 of
-  // peak against 0.735 at 3 on the 10 x 64 MiB + 4 x 64 MiB movement
-  const int grid = (int)std::min<uint64_t>(((uint64_t)a.n_tiles + 3) / 4, (uint64_t)n_cus * 8);
+  // 3 waves per SIMD: measured on the 10 x 64 MiB + 4 x 64 MiB movement
+  // 0.749 of peak at 2 or 3, 0.741 at 4, 0.735 at 8 (with the strips
+  // loaded 8 at a time; 16 or more at a time did no better)
+  const int grid = (int)std::min<uint64_t>(((uint64_t)a.n_tiles + 3) / 4, (uint64_t)n_cus * 3);
   return stream_launch(a, (uint32_t)n_out, grid, (hipStream_t)stream) == 0 ? EC_OK : EC_ERR_DEVICE;
 }
 

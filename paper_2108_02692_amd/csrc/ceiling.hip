@@ -26,6 +26,18 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ v4u load_nt(const void *p) { return __builtin_nontemporal_load((const v4u *)p); }
 __device__ __forceinline__ void store_nt(void *p, v4u v) { __builtin_nontemporal_store(v, (v4u *)p); }
 
+// Accesses at a block address held as an integer, in the global address
+// space: a pointer made from an integer is generic, and generic (flat)
+// loads here were each followed by a wait for all of them.
+typedef __attribute__((address_space(1))) const v4u global_cv4u;
+typedef __attribute__((address_space(1))) v4u global_v4u;
+__device__ __forceinline__ v4u load_nt_at(uint64_t base, uint64_t off) {
+  return __builtin_nontemporal_load((global_cv4u *)(base + off));
+}
+__device__ __forceinline__ void store_nt_at(uint64_t base, uint64_t off, v4u v) {
+  __builtin_nontemporal_store(v, (global_v4u *)(base + off));
+}
+
 constexpr int kCopyUnroll = 2;        // 16-byte elements per lane per step
 constexpr int kCopyGroupsPerCu = 16;  // workgroups of 256 lanes per compute unit
 
@@ -65,17 +77,15 @@ __global__ void __launch_bounds__(256) stream_kernel(ExecArgs a, uint32_t n_out)
     if (off >= sl) continue;  // lanes past the end of a ragged last tile
     v4u acc = {0u, 0u, 0u, 0u};
     for (uint32_t i = 0; i < a.n_in; ++i) {
-      const uint8_t *b = (const uint8_t *)(uintptr_t)a.blk[i] + off;
       v4u v[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) v[c] = load_nt(b + c * sl);
+      for (int c = 0; c < 8; ++c) v[c] = load_nt_at(a.blk[i], c * sl + off);
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc ^= v[c];
     }
     for (uint32_t j = 0; j < n_out; ++j) {
-      uint8_t *b = (uint8_t *)(uintptr_t)a.blk[a.n_in + j] + off;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) store_nt(b + c * sl, acc);
+      for (int c = 0; c < 8; ++c) store_nt_at(a.blk[a.n_in + j], c * sl + off, acc);
     }
   }
 }
