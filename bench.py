@@ -659,8 +659,8 @@ def bench_batched(args, stream):
     """8192 stripes mixing RS(6,3), RS(10,4), RS(12,4), RS(14,4); block sizes
     log-uniform 4 KiB .. 4 MiB in 512 B steps; 70% encodes, 30% decodes with
     uniformly drawn erasure sets; one persistent graph launch per step.
-    Inputs are slices of one seeded random pool (read-only, so stripes may
-    share bytes); every output is its own buffer."""
+    Every input block is its own range of one seeded random pool (no byte
+    read twice in a launch); every output is its own buffer."""
     from paper_2108_02692_amd import autotune, batching
 
     specs, pool, inputs, outputs, out_buf = batching.mixed_workload(args.batch_stripes, hi=args.batch_max_mib << 20)
@@ -693,7 +693,9 @@ def bench_batched_programs(args, stream):
     sets (up to 1470 programs), each of the same 8192 block sizes (multiples
     of 512 B, so a strip may start 64 B into a line), and the RS(10,4)
     encodes with the sizes rounded up to 1 KiB (every strip on a line
-    boundary); inputs drawn from the same pool.  Each batch: the time per
+    boundary); the RS(10,4) batches' inputs are consecutive 4 KiB-aligned
+    ranges of the mix's input pool (distinct bytes, wrapping to the start
+    only past its end).  Each batch: the time per
     launch and its algorithmic bytes (a byte-counter run of this command
     gives the fetched bytes per dispatch, in this order, 1 + max(3, steps /
     2) dispatches each)."""
@@ -711,13 +713,19 @@ def bench_batched_programs(args, stream):
     pats = [c for r in range(1, 5) for c in itertools.combinations(range(14), r)]
 
     def rs10_4(decode, align=512):
-        sp, ins, outs, off = [], [], [], 0
+        sp, ins, outs, off, cur = [], [], [], 0, 0
         for s0 in specs:
             bb = -(-s0.block_bytes // align) * align
             s = batching.StripeSpec(10, 4, bb, pats[int(rng.integers(len(pats)))] if decode else ())
             sp.append(s)
-            top = (pool.numel() - bb) // 4096
-            ins.append([pool[o:o + bb] for o in (rng.integers(0, top, 10) * 4096).tolist()])
+            span = -(-bb // 4096) * 4096
+            blocks = []
+            for _ in range(10):
+                if cur + bb > pool.numel():
+                    cur = 0
+                blocks.append(pool[cur:cur + bb])
+                cur += span
+            ins.append(blocks)
             outs.append([out_buf[off + j * bb: off + (j + 1) * bb] for j in range(s.n_out)])
             off += s.n_out * bb
         assert off <= out_buf.numel()

@@ -120,26 +120,42 @@ def mixed_specs(count: int, seed: int, codecs=CODECS_DEFAULT, lo=4096, hi=4 << 2
     return out
 
 
-def mixed_workload(count: int, seed: int = 4, hi: int = 4 << 20, pool_bytes: int = 4 << 30, slice_seed: int = 5):
+def mixed_workload(count: int, seed: int = 4, hi: int = 4 << 20, pool_bytes: int | None = None,
+                   slice_seed: int = 5):
     """The batched benchmark's stripes and buffers: ``mixed_specs(count,
-    seed, hi=hi)``; every input block a 4 KiB-aligned slice, at an offset
-    drawn from ``slice_seed``, of one pool of ``pool_bytes`` seeded random
-    bytes on the device (read-only, so stripes may share bytes); every
-    output block its own range of one output buffer.  Returns (specs, pool,
-    inputs, outputs, out_buf) with inputs[k] / outputs[k] lists of tensor
-    views in program argument order."""
+    seed, hi=hi)``; the input blocks lie in one pool of seeded random bytes
+    on the device.  With ``pool_bytes`` None (the benchmark) every input
+    block has its own 4 KiB-aligned range of a pool as large as all of
+    them, in stripe order, as distinct objects would: no byte is read twice
+    in a launch, so no read can be served by the memory-side cache.  With
+    ``pool_bytes`` (tests that want a small host copy) each input block is a
+    4 KiB-aligned slice of a pool of that size at an offset drawn from
+    ``slice_seed``, and stripes share bytes.  Every output block has its own
+    range of one output buffer.  Returns (specs, pool, inputs, outputs,
+    out_buf) with inputs[k] / outputs[k] lists of tensor views in program
+    argument order."""
     import torch
     specs = mixed_specs(count, seed=seed, hi=hi)
+    def span(b):
+        return -(-b // 4096) * 4096
+    distinct = pool_bytes is None
+    if distinct:
+        pool_bytes = sum(s.n_in * span(s.block_bytes) for s in specs)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
     rng = np.random.default_rng(slice_seed)
     out_total = sum(s.n_out * s.block_bytes for s in specs)
     out_buf = torch.empty(out_total, dtype=torch.uint8, device="cuda")
-    inputs, outputs, off = [], [], 0
+    inputs, outputs, off, cursor = [], [], 0, 0
     for s in specs:
-        top = (pool_bytes - s.block_bytes) // 4096
-        inputs.append([pool[o:o + s.block_bytes] for o in (rng.integers(0, top, s.n_in) * 4096).tolist()])
+        if distinct:
+            offs = [cursor + i * span(s.block_bytes) for i in range(s.n_in)]
+            cursor += s.n_in * span(s.block_bytes)
+        else:
+            top = (pool_bytes - s.block_bytes) // 4096
+            offs = (rng.integers(0, top, s.n_in) * 4096).tolist()
+        inputs.append([pool[o:o + s.block_bytes] for o in offs])
         outputs.append([out_buf[off + j * s.block_bytes: off + (j + 1) * s.block_bytes] for j in range(s.n_out)])
         off += s.n_out * s.block_bytes
     return specs, pool, inputs, outputs, out_buf

@@ -295,22 +295,31 @@ __global__ void __launch_bounds__(256) slp_exec_kernel_%(K)d(ExecArgs a) {
   }
 }
 
-// Waves take work items from a device counter, `chunk` consecutive items
-// per atomic add.  An item covers tiles_per_item tiles of its stripe.
-// Items, descriptors and block tables are read through the scalar cache;
-// the block table is rebuilt only when the stripe changes.  The host lists
-// a stripe's tiles consecutively.
+// Workgroups take work items from a device counter, 4 `chunk`s of
+// consecutive items per atomic add, and wave w of the workgroup runs chunk
+// w: the host lists a stripe's tiles consecutively, so the 4 waves of a
+// compute unit run neighbouring tiles side by side, and a cache line that
+// two neighbouring tiles share (a strip that starts off a 128-byte line)
+// is fetched once into that unit's L2 rather than by two units.  Every
+// wave leaves the loop on the same shared value, so each reaches every
+// barrier.  An item covers tiles_per_item tiles of its stripe.  Items,
+// descriptors and block tables are read through the scalar cache; the
+// block table is rebuilt only when the stripe changes.
 __global__ void __launch_bounds__(256) slp_batch_kernel_%(K)d(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t voff = lane * 16u;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  __shared__ uint32_t group_first;
   %(DECLS)s
   EC_INIT_%(K)d;
   uint32_t cur = 0xffffffffu, tab_lo = 0, tab_hi = 0;
   for (;;) {
-    uint32_t first = 0;
-    if (lane == 0) first = atomicAdd(a.counter, a.chunk);
-    first = __builtin_amdgcn_readfirstlane(first);
-    if (first >= a.n_items) break;
+    if (threadIdx.x == 0) group_first = atomicAdd(a.counter, 4u * a.chunk);
+    __syncthreads();
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)group_first);
+    __syncthreads();  // every wave has read it before the next add writes it
+    if (base >= a.n_items) break;
+    const uint32_t first = base + wave * a.chunk;
     const uint32_t last = min(first + a.chunk, a.n_items);
     for (uint32_t it = first; it < last; ++it) {
       const uint32_t stripe = ((ConstU32Ptr)(uintptr_t)a.items)[2 * it];

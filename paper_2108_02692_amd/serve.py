@@ -102,10 +102,12 @@ class Server:
         return wall
 
 
-def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool_bytes: int,
+def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int | None = None, pool_bytes: int = 0,
                   ratio_10_4=0.75, encode_frac=0.7, median=256 << 10, sigma=1.0, lo=4 << 10, hi=MAX_OBJECT):
-    """Seeded Poisson arrivals over ``duration_s``; inputs point into a
-    read-only device pool."""
+    """Seeded Poisson arrivals over ``duration_s``.  With ``pool_ptr`` the
+    inputs are 4 KiB-aligned slices of that read-only device pool at offsets
+    drawn with the arrivals (requests share bytes); without, they are left
+    empty for ``place_inputs``."""
     import itertools
     rng = np.random.default_rng(seed)
     t, reqs = 0.0, []
@@ -122,9 +124,35 @@ def make_requests(duration_s: float, rate: float, seed: int, pool_ptr: int, pool
             if (n, p) not in pats:
                 pats[(n, p)] = [c for r in range(1, p + 1) for c in itertools.combinations(range(n + p), r)]
             erased = pats[(n, p)][int(rng.integers(len(pats[(n, p)])))]
-        offs = rng.integers(0, (pool_bytes - bb) // 4096, n) * 4096
-        reqs.append(Request(len(reqs), t, n, p, erased, bb, inputs=[pool_ptr + int(o) for o in offs]))
+        inputs = []
+        if pool_ptr is not None:
+            offs = rng.integers(0, (pool_bytes - bb) // 4096, n) * 4096
+            inputs = [pool_ptr + int(o) for o in offs]
+        reqs.append(Request(len(reqs), t, n, p, erased, bb, inputs=inputs))
     return reqs
+
+
+def _span(block_bytes: int) -> int:
+    return -(-block_bytes // 4096) * 4096
+
+
+def input_span(reqs) -> int:
+    """Bytes of the pool ``place_inputs`` needs for ``reqs``."""
+    return sum(r.n * _span(r.block_bytes) for r in reqs)
+
+
+def place_inputs(reqs, pool_ptr: int, pool_bytes: int):
+    """Gives every request's input blocks their own 4 KiB-aligned ranges of
+    the device pool, in arrival order, as distinct objects would have: no
+    two requests share input bytes, so no read is served by the memory-side
+    cache from another request's read."""
+    cur = 0
+    for r in reqs:
+        sp = _span(r.block_bytes)
+        r.inputs = [pool_ptr + cur + i * sp for i in range(r.n)]
+        cur += r.n * sp
+    if cur > pool_bytes:
+        raise ValueError("pool of %d bytes holds less than the %d bytes of inputs" % (pool_bytes, cur))
 
 
 def batched_reference(server, requests, chunk=8192, reps=3):
@@ -170,15 +198,17 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     busy for a while (the caller's choice of work, finished before it
     returns) and the drain is run again (``drain_GB_s``)."""
     import torch
-    pool_bytes = 1 << 30
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
     t_setup = time.perf_counter()
     if server is None:
         server = Server(budget_bytes=budget_bytes, n_slots=n_slots, max_batch=max_batch, slots=slots)
     setup_s = time.perf_counter() - t_setup
-    reqs = make_requests(duration_s, rate, seed, pool.data_ptr(), pool_bytes)
+    # every request's inputs are bytes of their own (seeded random)
+    reqs = make_requests(duration_s, rate, seed)
+    pool_bytes = input_span(reqs)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    pool = torch.randint(0, 256, (pool_bytes,), dtype=torch.uint8, device="cuda", generator=g)
+    place_inputs(reqs, pool.data_ptr(), pool_bytes)
     torch.cuda.synchronize()
     # no collector pauses inside the timed loop (the request objects are
     # all allocated beforehand)
@@ -229,5 +259,7 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
         res.update({"drain_s": d, "drain_GB_s": in_bytes / d / 1e9, "drain_launches": launches})
         ref = batched_reference(server, reqs)
         res.update({"batched_same_GB_s": ref, "drain_vs_batched_same": in_bytes / d / 1e9 / ref})
+    res["input_pool_bytes"] = pool_bytes
     del pool
+    torch.cuda.empty_cache()
     return res

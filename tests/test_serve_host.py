@@ -24,3 +24,21 @@ def test_request_stream_shape():
     assert 200 << 10 < np.median(obj) < 330 << 10             # log-normal median 256 KiB (+ rounding)
     again = make_requests(0.5, 20000.0, seed=7, pool_ptr=1 << 40, pool_bytes=1 << 30)
     assert [(r.arrival, r.block_bytes, r.erased) for r in again] == [(r.arrival, r.block_bytes, r.erased) for r in reqs]
+
+
+def test_distinct_input_layout():
+    """place_inputs: every input block its own 4 KiB-aligned range of the
+    pool (no two blocks overlap), inside the pool; a pool too small is an
+    error."""
+    import pytest
+    from paper_2108_02692_amd.serve import input_span, place_inputs
+    reqs = make_requests(0.05, 20000.0, seed=3)
+    assert reqs and all(r.inputs == [] for r in reqs)
+    base, need = 1 << 40, input_span(reqs)
+    place_inputs(reqs, base, need)
+    spans = sorted((x, x + r.block_bytes) for r in reqs for x in r.inputs)
+    assert len(spans) == sum(r.n for r in reqs)
+    assert all(a % 4096 == 0 and base <= a and b <= base + need for a, b in spans)
+    assert all(b0 <= a1 for (_, b0), (a1, _) in zip(spans, spans[1:]))
+    with pytest.raises(ValueError):
+        place_inputs(reqs, base, need - 4096)
