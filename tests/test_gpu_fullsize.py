@@ -179,19 +179,22 @@ def test_segment_order_single_launch_and_batch():
             first_diff(rec[j].cpu().numpy(), want_dec[er.index(e)], "%s decode block %d" % (mode, e))
 
 
-@pytest.mark.parametrize("n,p,er,K", [(12, 6, (), 48), (12, 6, (0, 3, 7, 12, 16, 17), 48), (4, 12, (), 0),
-                                      (12, 6, (), 0), (12, 6, (0, 3, 7, 12, 16, 17), 0), (10, 6, (), 0)])
-def test_wide_codecs_64mib_every_byte(n, p, er, K):
+@pytest.mark.parametrize("n,p,er,K,native", [(12, 6, (), 48, 0), (12, 6, (0, 3, 7, 12, 16, 17), 48, 0),
+                                             (4, 12, (), 0, 0), (12, 6, (), 0, 0), (12, 6, (0, 3, 7, 12, 16, 17), 0, 0),
+                                             (10, 6, (), 0, 0), (12, 6, (), 0, 1), (10, 6, (1, 4, 9, 11, 13, 15), 0, 1)])
+def test_wide_codecs_64mib_every_byte(n, p, er, K, native):
     """Codecs with more rows than 48 slots hold: by default a 56- or
     60-slot program in one pass where the rows fit, else (and with 48 slots
     forced) several passes run as pass parts, the library's default for such
-    stripes.  64 MiB blocks, every byte of every output against the oracle."""
+    stripes; the one-pass programs also as native kernels.  64 MiB blocks,
+    every byte of every output against the oracle."""
     S = 64 << 20
     G = oracle.cauchy(n, p)
     data = W.device_blocks(n, S, seed=n + 7 * p)
     host = [d.cpu().numpy() for d in data]
     par = oracle.encode(G, n, p, host, threads=THREADS)
-    prog = E.ec_compile_slp(n, p, gen_rows(n, p), list(er), slot_budget=K)
+    prog = E.ec_compile_slp(n, p, gen_rows(n, p), list(er), slot_budget=K, native=native)
+    assert prog.info["native"] == native
     if K == 48 or (n, p) == (4, 12):
         assert prog.info["passes"] > 1 and prog.info["n_pass_parts"] >= prog.info["passes"]
     else:
