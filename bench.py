@@ -524,8 +524,8 @@ def bench_codecs(args, stream):
     paper's throughput comparison, with Cauchy matrices): encode, and decode
     of the worst set of p lost data blocks, each compressed and plain, on
     d blocks of 64 MiB resident in HBM, with the headline's executor and
-    buffer rotation (the outputs rotate over --rotate-out sets; the
-    programs are compiled on host threads first)."""
+    buffer rotation (inputs over --rotate-in sets, outputs over
+    --rotate-out sets; the programs are compiled on host threads first)."""
     from concurrent.futures import ThreadPoolExecutor
     import torch
     import paper_2108_02692_amd as E
@@ -543,7 +543,8 @@ def bench_codecs(args, stream):
     for (n, p) in codecs:
         gen = gens[(n, p)]
         er = ers[(n, p)]
-        data = W.device_blocks(n, S, seed=100 + 10 * n + p)
+        data_sets = [W.device_blocks(n, S, seed=100 + 10 * n + p + 1000 * r) for r in range(max(1, args.rotate_in))]
+        data = data_sets[0]
         par_sets = [W.empty_blocks(p, S) for _ in range(max(1, args.rotate_out))]
         parity = par_sets[0]
         rec_sets = [W.empty_blocks(p, S) for _ in range(max(1, args.rotate_out))]
@@ -552,7 +553,7 @@ def bench_codecs(args, stream):
         ref = None
         for level, tag in ((E.LEVEL_CO_FU_SCHED, "comp"), (E.LEVEL_PLAIN, "plain")):
             enc = progs[((n, p), level, ())]
-            ms = time_launches(rotating(lambda i, o: E.ec_encode(enc, i, o, S, stream), [data], par_sets),
+            ms = time_launches(rotating(lambda i, o: E.ec_encode(enc, i, o, S, stream), data_sets, par_sets),
                                args.steps, args.warmup, stream)
             E.ec_encode(enc, data, parity, S, stream)
             torch.cuda.synchronize()
@@ -566,7 +567,13 @@ def bench_codecs(args, stream):
             dec = progs[((n, p), level, tuple(er))]
             blocks = data + ref
             surv = [blocks[i] for i in dec.in_blocks]
-            ms = time_launches(rotating(lambda i, o: E.ec_decode(dec, i, o, S, stream), [surv], rec_sets),
+            if level == E.LEVEL_CO_FU_SCHED:  # the survivors of every input set (parity of each)
+                surv_sets = [surv]
+                for d in data_sets[1:]:
+                    par_d = W.empty_blocks(p, S)
+                    E.ec_encode(enc, d, par_d, S, stream)
+                    surv_sets.append([(d + par_d)[i] for i in dec.in_blocks])
+            ms = time_launches(rotating(lambda i, o: E.ec_decode(dec, i, o, S, stream), surv_sets, rec_sets),
                                args.steps, args.warmup, stream)
             E.ec_decode(dec, surv, rec, S, stream)
             torch.cuda.synchronize()
@@ -579,7 +586,7 @@ def bench_codecs(args, stream):
         log("%s: enc %.1f GB/s dec %.1f GB/s" % (row["codec"], row["enc_comp"]["GB_s"],
                                                   row["dec_comp"]["GB_s"]))
         rows.append(row)
-        del data, parity, rec, ref, blocks, surv, par_sets, rec_sets
+        del data, data_sets, parity, rec, ref, blocks, surv, surv_sets, par_sets, rec_sets
         torch.cuda.empty_cache()
     return rows
 
