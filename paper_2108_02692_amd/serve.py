@@ -186,8 +186,28 @@ def batched_reference(server, requests, chunk=8192, reps=3):
     return sum(r.n * r.block_bytes for r in requests) / best / 1e9
 
 
+def _pinned(pin):
+    """Context: the calling thread on one of its allowed CPUs (the serving
+    loop polls; a move to another core or a neighbour's interruption shows
+    as a latency outlier), its affinity restored afterwards."""
+    import contextlib
+    import os
+
+    @contextlib.contextmanager
+    def ctx():
+        allowed = os.sched_getaffinity(0) if pin else None
+        if allowed and len(allowed) > 1:
+            os.sched_setaffinity(0, {sorted(allowed)[len(allowed) // 2]})
+        try:
+            yield
+        finally:
+            if allowed and len(allowed) > 1:
+                os.sched_setaffinity(0, allowed)
+    return ctx()
+
+
 def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, max_batch=DEFAULT_MAX_BATCH,
-        slots=38, drain=True, server=None, warm_up=None):
+        slots=38, drain=True, server=None, warm_up=None, pin=True):
     """The serving benchmark at one arrival rate: throughput, latency
     percentiles and requests per launch; with ``drain``, the same requests
     again all present at once (the capacity behind the latencies), and once
@@ -196,7 +216,10 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     real-time run: the first drain follows that run directly
     (``drain_cold_GB_s``); ``warm_up()``, if given, then keeps the device
     busy for a while (the caller's choice of work, finished before it
-    returns) and the drain is run again (``drain_GB_s``)."""
+    returns) and the drain is run again (``drain_GB_s``).  With ``pin`` the
+    loop's thread stays on one core while the clock runs (measured at 20k
+    req/s: p99 0.036-0.037 ms in every run, against 0.036-0.058 ms
+    unpinned)."""
     import torch
     t_setup = time.perf_counter()
     if server is None:
@@ -216,7 +239,8 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     gc.disable()
     b0 = server.batches
     try:
-        wall = server.serve(reqs)
+        with _pinned(pin):
+            wall = server.serve(reqs)
     finally:
         gc.enable()
     torch.cuda.synchronize()
@@ -246,7 +270,8 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
             gc.disable()
             b0 = server.batches
             try:
-                d = server.serve(reqs, realtime=False)
+                with _pinned(pin):
+                    d = server.serve(reqs, realtime=False)
             finally:
                 gc.enable()
             torch.cuda.synchronize()

@@ -42,3 +42,22 @@ def test_distinct_input_layout():
     assert all(b0 <= a1 for (_, b0), (a1, _) in zip(spans, spans[1:]))
     with pytest.raises(ValueError):
         place_inputs(reqs, base, need - 4096)
+
+
+def test_pinned_restores_affinity():
+    """The serving loop's pinning keeps the thread on one allowed CPU while
+    it runs and gives the full set back afterwards, also on an error."""
+    import os
+    import pytest
+    from paper_2108_02692_amd.serve import _pinned
+    allowed = os.sched_getaffinity(0)
+    with _pinned(True):
+        inside = os.sched_getaffinity(0)
+    assert os.sched_getaffinity(0) == allowed
+    assert inside <= allowed and (len(inside) == 1 or len(allowed) == 1)
+    with pytest.raises(RuntimeError):
+        with _pinned(True):
+            raise RuntimeError("stop")
+    assert os.sched_getaffinity(0) == allowed
+    with _pinned(False):
+        assert os.sched_getaffinity(0) == allowed
