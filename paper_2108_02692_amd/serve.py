@@ -218,8 +218,8 @@ def run(duration_s=2.0, rate=20000.0, seed=7, budget_bytes=16 << 30, n_slots=4, 
     busy for a while (the caller's choice of work, finished before it
     returns) and the drain is run again (``drain_GB_s``).  With ``pin`` the
     loop's thread stays on one core while the clock runs (measured at 20k
-    req/s: p99 0.036-0.037 ms in every run, against 0.036-0.058 ms
-    unpinned)."""
+    req/s: p99 within 0.002 ms from run to run on a box, 0.036-0.057 ms
+    over three boxes, against 0.036-0.088 ms unpinned)."""
     import torch
     t_setup = time.perf_counter()
     if server is None:
